@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs for one Newton linear solve of implicit elastodynamics.
+
+This module builds the *inputs* of the in-solve coarsening path: a tetrahedral
+mesh, its edge list, per-element 12x12 Hessian blocks, the per-DoF gradient,
+the per-edge collapse tags, and (for the contact case) point-triangle barrier
+blocks.  It holds none of the arithmetic of the coarsening method (no
+aggregation, no Galerkin product, no solve); both the GPU library and the CPU
+oracle consume what it returns.
+
+The paper solves H d = -grad E with H an SPD proxy of the incremental
+potential's Hessian (Sec. 3, Eq. 1-2): H = M/h^2 + (elastic Hessian) +
+(contact Hessian).  Here the elastic part of every tetrahedron is the
+co-rotated linear-elastic stiffness R K0 R^T at a random per-element rotation,
+and the lumped mass rho*V/4 per element vertex, divided by h^2, is folded into
+the element block so that every element block is SPD on its own.
+
+Edge tags follow the paper's tag semantics (Sec. 4.1; supplement Sec. 1.1):
+1 = collapsible, 0 = protected.  A smooth random field stands in for the
+Green-strain-increment criterion (Sec. 4.2, Eq. 3): an edge is collapsible
+when the mean of the field at its two endpoints ranks among the lowest
+``frac`` of all edges.
+
+Random streams: ``np.random.default_rng(SeedSequence([seed, stream]))`` with
+stream 0 rotations, 1 field, 2 gradient, 3 adjoint seed w, 4 finite-difference
+directions, 5 jitter, 6 contact, 7 drift.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+YOUNG = 1.0e5
+POISSON = 0.4
+DENSITY = 1000.0
+H_STEP = 1.0e-2
+
+S_ROT, S_FIELD, S_GRAD, S_W, S_FD, S_JITTER, S_CONTACT, S_DRIFT = range(8)
+
+
+def rng_for(seed: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(stream)]))
+
+
+def lame(young: float = YOUNG, poisson: float = POISSON) -> tuple[float, float]:
+    mu = young / (2.0 * (1.0 + poisson))
+    lam = young * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson))
+    return mu, lam
+
+
+# --------------------------------------------------------------------------
+# mesh
+# --------------------------------------------------------------------------
+
+# corner code c = dx + 2*dy + 4*dz inside one cube
+_C = {(0, 0, 0): 0, (1, 0, 0): 1, (0, 1, 0): 2, (1, 1, 0): 3,
+      (0, 0, 1): 4, (1, 0, 1): 5, (0, 1, 1): 6, (1, 1, 1): 7}
+
+
+def _tets(spec):
+    return np.array([[_C[tuple(int(ch) for ch in v)] for v in t.split()] for t in spec], dtype=np.int64)
+
+
+# 5-tet split without an interior diagonal; odd cubes use the mirror split so
+# that the face diagonals of neighbouring cubes coincide.
+_EVEN = _tets(["000 110 101 011", "100 000 110 101", "010 110 000 011",
+               "001 101 011 000", "111 011 101 110"])
+_ODD = _tets(["100 010 001 111", "000 100 010 001", "110 010 100 111",
+              "101 001 111 100", "011 111 001 010"])
+
+
+def box_mesh(nx: int, ny: int, nz: int, cell: float, origin=(0.0, 0.0, 0.0)):
+    """Vertices and tets of an nx*ny*nz grid of cubes (edge ``cell``), 5 tets per cube.
+
+    Vertex id = i + (nx+1)*(j + (ny+1)*k).  Tets are positively oriented.
+    """
+    vx, vy, vz = nx + 1, ny + 1, nz + 1
+    k, j, i = np.meshgrid(np.arange(vz), np.arange(vy), np.arange(vx), indexing="ij")
+    pos = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64) * cell
+    pos += np.asarray(origin, dtype=np.float64)[None, :]
+
+    ck, cj, ci = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
+    corner = np.empty((ci.size, 8), dtype=np.int64)
+    for (dx, dy, dz), c in _C.items():
+        corner[:, c] = (ci + dx) + vx * ((cj + dy) + vy * (ck + dz))
+    odd = ((ci + cj + ck) & 1).astype(bool)
+    table = np.where(odd[:, None, None], _ODD[None], _EVEN[None])        # (ncube,5,4)
+    tets = np.take_along_axis(corner[:, None, :], table, axis=2).reshape(-1, 4)
+
+    d = pos[tets[:, 1:]] - pos[tets[:, :1]]
+    neg = np.linalg.det(d) < 0
+    tets[neg] = tets[neg][:, [0, 1, 3, 2]]
+    return pos, tets.astype(np.int32)
+
+
+def mesh_edges(tets: np.ndarray, n_verts: int) -> np.ndarray:
+    """Unique undirected edges of a tet mesh as sorted (lo, hi) int32 pairs."""
+    t = tets.astype(np.int64)
+    pairs = np.concatenate([t[:, [a, b]] for a in range(4) for b in range(a + 1, 4)], axis=0)
+    lo = pairs.min(axis=1)
+    hi = pairs.max(axis=1)
+    key = np.unique(lo * n_verts + hi)
+    return np.stack([key // n_verts, key % n_verts], axis=1).astype(np.int32)
+
+
+def grid_counts(nx: int, ny: int, nz: int) -> dict:
+    """Closed-form sizes of the 5-tet grid (used by the tests)."""
+    nv = (nx + 1) * (ny + 1) * (nz + 1)
+    axis = nx * (ny + 1) * (nz + 1) + (nx + 1) * ny * (nz + 1) + (nx + 1) * (ny + 1) * nz
+    diag = nx * ny * (nz + 1) + nx * (ny + 1) * nz + (nx + 1) * ny * nz
+    return {"n_verts": nv, "n_tets": 5 * nx * ny * nz, "n_edges": axis + diag}
+
+
+# --------------------------------------------------------------------------
+# element blocks
+# --------------------------------------------------------------------------
+
+def shape_gradients(pos: np.ndarray, tets: np.ndarray):
+    """Per-tet volume and gradients of the 4 linear shape functions, (n,) and (n,4,3)."""
+    x = pos[tets]
+    dm = np.stack([x[:, 1] - x[:, 0], x[:, 2] - x[:, 0], x[:, 3] - x[:, 0]], axis=-1)
+    vol = np.abs(np.linalg.det(dm)) / 6.0
+    inv = np.linalg.inv(dm)                 # rows: grad N_1..N_3
+    grads = np.empty((tets.shape[0], 4, 3))
+    grads[:, 1:] = inv
+    grads[:, 0] = -inv.sum(axis=1)
+    return vol, grads
+
+
+def linear_stiffness(vol, grads, mu, lam):
+    """Rest-pose linear-elastic stiffness blocks K0[n,a,b] (3x3), psi = mu eps:eps + lam/2 tr(eps)^2."""
+    gg = np.einsum("nai,nbi->nab", grads, grads)
+    eye = np.eye(3)
+    k = mu * gg[:, :, :, None, None] * eye
+    k = k + mu * np.einsum("nbm,nap->nabmp", grads, grads)
+    k = k + lam * np.einsum("nam,nbp->nabmp", grads, grads)
+    return k * vol[:, None, None, None, None]
+
+
+def random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Uniform rotations from normalised 4-D Gaussian quaternions (Shoemake)."""
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    r = np.empty((n, 3, 3))
+    r[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    r[:, 0, 1] = 2 * (x * y - z * w)
+    r[:, 0, 2] = 2 * (x * z + y * w)
+    r[:, 1, 0] = 2 * (x * y + z * w)
+    r[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    r[:, 1, 2] = 2 * (y * z - x * w)
+    r[:, 2, 0] = 2 * (x * z - y * w)
+    r[:, 2, 1] = 2 * (y * z + x * w)
+    r[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return r
+
+
+def elastic_blocks(pos, tets, rot, mu, lam, rho, h, out=None, chunk=1 << 17):
+    """12x12 row-major element blocks (DoF order 3a+k): R K0 R^T + rho V/(4 h^2) I, symmetrised."""
+    n = tets.shape[0]
+    if out is None:
+        out = np.empty((n, 144), dtype=np.float64)
+    for s in range(0, n, chunk):
+        e = slice(s, min(n, s + chunk))
+        vol, grads = shape_gradients(pos, tets[e])
+        k0 = linear_stiffness(vol, grads, mu, lam)                     # (m,4,4,3,3)
+        r = rot[e][:, None, None]
+        kr = r @ k0 @ np.swapaxes(r, -1, -2)
+        blk = kr.transpose(0, 1, 3, 2, 4).reshape(-1, 12, 12)
+        blk += (rho * vol / (4.0 * h * h))[:, None, None] * np.eye(12)
+        blk = 0.5 * (blk + np.swapaxes(blk, 1, 2))
+        out[e] = blk.reshape(-1, 144)
+    return out
+
+
+def lumped_mass(tets, vol, rho, n_verts):
+    return np.bincount(tets.ravel().astype(np.int64), weights=np.repeat(rho * vol / 4.0, 4),
+                       minlength=n_verts)
+
+
+# --------------------------------------------------------------------------
+# tags
+# --------------------------------------------------------------------------
+
+def fourier_field(rng: np.random.Generator, n_modes: int = 4):
+    """Smooth scalar field: sum of n_modes cosines, 1-3 cycles per unit length."""
+    amp = rng.standard_normal(n_modes)
+    d = rng.standard_normal((n_modes, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    k = d * rng.uniform(1.0, 3.0, size=(n_modes, 1))
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
+    return {"amp": amp, "k": k, "phase": phase}
+
+
+def eval_field(field, pos, shift=None):
+    p = pos if shift is None else pos - shift[None, :]
+    arg = 2.0 * math.pi * (p @ field["k"].T) + field["phase"][None, :]
+    return np.cos(arg) @ field["amp"]
+
+
+def rank_tags(values: np.ndarray, frac: float) -> np.ndarray:
+    """1 for the floor(frac*E) edges with the smallest value (ties by edge id), else 0."""
+    order = np.argsort(values, kind="stable")
+    tags = np.zeros(values.shape[0], dtype=np.uint8)
+    tags[order[: int(math.floor(frac * values.shape[0]))]] = 1
+    return tags
+
+
+def edge_tags(field, pos, edges, frac, shift=None):
+    f = eval_field(field, pos, shift)
+    return rank_tags(0.5 * (f[edges[:, 0]] + f[edges[:, 1]]), frac)
+
+
+# --------------------------------------------------------------------------
+# problems
+# --------------------------------------------------------------------------
+
+def grid_problem(n: int, seed: int, frac: float, young: float = YOUNG, poisson: float = POISSON,
+                 rho: float = DENSITY, h: float = H_STEP) -> dict:
+    """Unit cube as an n^3 grid of cubes, 5 tets each, co-rotated stiffness + lumped mass."""
+    pos, tets = box_mesh(n, n, n, 1.0 / n)
+    nv = pos.shape[0]
+    edges = mesh_edges(tets, nv)
+    mu, lam = lame(young, poisson)
+    rot = random_rotations(rng_for(seed, S_ROT), tets.shape[0])
+    elem_h = elastic_blocks(pos, tets, rot, mu, lam, rho, h)
+    vol, _ = shape_gradients(pos, tets)
+    field = fourier_field(rng_for(seed, S_FIELD))
+    tags = edge_tags(field, pos, edges, frac)
+    g = rng_for(seed, S_GRAD).standard_normal((nv, 3))
+    return {
+        "name": f"grid{n}", "n_verts": nv, "pos": pos, "edges": edges, "tags": tags,
+        "elem_verts": tets, "elem_H": elem_h, "g": g, "h": h,
+        "mass": lumped_mass(tets, vol, rho, nv), "field": field, "frac": frac, "seed": seed,
+    }
+
+
+# The measured workloads (cube grids of 5 tets/cube).
+CONFIGS = {
+    "c1": dict(n=8, seed=1, frac=0.7),      # 729 vertices, 2560 tets, FP64, PCG rtol 1e-10
+    "c2": dict(n=64, seed=2, frac=0.6),     # 274,625 vertices, 1.31M tets, FP64 and mixed
+    "c4": dict(n=32, seed=4, frac=0.7),     # 35,937 vertices, adjoint
+    "c5": dict(n=128, seed=5, frac=0.6),    # 2.15M vertices, re-aggregation
+}
+
+
+def make_config(name: str) -> dict:
+    c = CONFIGS[name]
+    p = grid_problem(c["n"], c["seed"], c["frac"])
+    p["name"] = name
+    return p
+
+
+def adjoint_seed(p: dict) -> np.ndarray:
+    return rng_for(p["seed"], S_W).standard_normal((p["n_verts"], 3))
+
+
+def random_graph(rng: np.random.Generator, n: int, m: int, p_tag: float = 0.5):
+    """Random multigraph with self-loops and duplicates, for aggregation tests."""
+    if n == 0:
+        return np.zeros((0, 2), np.int32), np.zeros(0, np.uint8)
+    e = rng.integers(0, n, size=(m, 2)).astype(np.int32)
+    t = (rng.random(m) < p_tag).astype(np.uint8)
+    return e, t
