@@ -1,0 +1,242 @@
+/*
+ * agc.h - in-solve algebraic coarsening for one Newton linear solve of
+ * implicit IPC, on AMD MI355X (gfx950).
+ *
+ * The method (Wang et al., "AGIPC: Adaptive In-Solve Algebraic Coarsening for
+ * GPU IPC", SIGGRAPH 2026) replaces the Newton system H d = -g (Sec. 3,
+ * Eq. 2) by a Galerkin coarse system built from per-edge collapse tags:
+ *
+ *   map  : fine vertex -> super-node, connected components of the graph of
+ *          collapsible edges (Sec. 4.1; supplement Sec. 1, Alg. 1-2)
+ *   A_c  = P^T H P,  b_c = P^T g      (Sec. 4.1, Galerkin equivalence)
+ *   x_c  = A_c^{-1} b_c by 3x3 block-Jacobi PCG   (Alg. overview; Sec. 5.1)
+ *   x    = P x_c                      (Sec. 4.3, prolongation)
+ *
+ * P is the 3n x 3n_c 0/1 matrix with P[3v+i][3 map(v)+i] = 1 (the paper's
+ * restriction U is P^T).  The library returns x = P A_c^{-1} P^T g; the Newton
+ * direction is d = -x.
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers unless marked [host].  They are
+ *    owned by the caller, must stay valid until the call's work on the
+ *    context's stream has finished, and are never freed by the library.
+ *  - Work is enqueued on the context's HIP stream.  Calls that return a
+ *    [host] value synchronise that stream before returning.
+ *  - Every call returns an agc_status.  No C++ exception crosses this ABI.
+ *    On a non-OK status agc_last_error() describes the failure.
+ *  - Vectors of vertices are [n][3] float64, DoF order 3v+k.
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - HIP errors (including a failed allocation) leave the context usable
+ *    only for agc_destroy and agc_last_error.
+ */
+#ifndef AGC_H
+#define AGC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t agc_status;
+enum {
+  AGC_OK = 0,
+  AGC_ERR_INVALID_ARG = -1,   /* null pointer, negative size, bad enum: nothing was enqueued    */
+  AGC_ERR_OUT_OF_MEMORY = -2, /* device allocation failed                                       */
+  AGC_ERR_DEVICE = -3,        /* a HIP runtime call failed                                      */
+  AGC_ERR_NOT_CONVERGED = -4, /* PCG hit max_iter: x holds the last iterate                     */
+  AGC_ERR_NOT_SPD = -5,       /* a 3x3 diagonal block is not SPD, p^T A p <= 0, or NaN/Inf seen */
+  AGC_ERR_BAD_INPUT = -6      /* device data out of range: vertex id, tag not 0/1, etc.         */
+};
+
+enum { AGC_F64 = 0, AGC_F32 = 1 };                 /* element / matrix value type */
+enum { AGC_PREC_FP64 = 0, AGC_PREC_MIXED = 1 };    /* solve precision            */
+
+typedef struct agc_context agc_context; /* owns workspace, binds one device + stream     */
+typedef struct agc_mesh agc_mesh;       /* static element topology (built once per mesh) */
+typedef struct agc_matrix agc_matrix;   /* assembled BSR 3x3 matrix, device resident     */
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the legacy default stream).  *ctx receives the handle. */
+agc_status agc_create(agc_context** ctx, int32_t device, void* stream);
+agc_status agc_set_stream(agc_context* ctx, void* stream);
+/* Frees the context's workspace.  Matrices and meshes must be destroyed first. */
+agc_status agc_destroy(agc_context* ctx);
+/* [host] Text of the last failure on this context ("" if none).  Valid until
+ * the next call on the context. */
+const char* agc_last_error(const agc_context* ctx);
+/* [host] Library version string. */
+const char* agc_version(void);
+
+/* ------------------------------------------------------------------- mesh */
+
+/* Precomputes the static structure of a mesh of `n_elems` four-vertex
+ * elements (tetrahedra, or point-triangle contact stencils).  In the method
+ * the fine connectivity never changes between Newton iterations; only the
+ * tags, the map and the values do (Sec. 4.1).  So the fine block pattern,
+ * the order in which element sub-blocks are summed into each fine block, and
+ * the vertex-element incidence are computed here once.
+ *   elem_verts : [n_elems][4] int32, four distinct ids in [0, n_verts).
+ * Returns AGC_ERR_BAD_INPUT if an id is out of range or repeated in an
+ * element.  Synchronises the stream. */
+agc_status agc_mesh_create(agc_context* ctx, int32_t n_verts, int64_t n_elems,
+                           const int32_t* elem_verts, agc_mesh** mesh);
+agc_status agc_mesh_destroy(agc_context* ctx, agc_mesh* mesh);
+/* [host] sizes: vertices, elements, fine blocks in the full symmetric pattern. */
+agc_status agc_mesh_info(const agc_mesh* mesh, int32_t* n_verts, int64_t* n_elems,
+                         int64_t* fine_nnzb);
+
+/* -------------------------------------------------------------- (a) map */
+
+/* Fine-to-coarse aggregation (Sec. 4.1; supplement Sec. 1): super-nodes are
+ * the connected components of the graph whose edges are the collapsible
+ * ones.  Labels are canonical: component c is the c-th in increasing order of
+ * its smallest vertex id, which is the order the supplement's elected-lane
+ * popcount and group prefix sum produce (supplement Alg. 2, Sec. 1.3).
+ *   edges    : [n_edges][2] int32 vertex ids, unordered; duplicates and
+ *              self-loops allowed (a self-loop joins nothing).
+ *   tags     : [n_edges] uint8, 1 = collapsible, 0 = protected.
+ *   map      : [n_verts] int32 out.
+ *   n_coarse : [host] out, number of super-nodes.  Synchronises.
+ * AGC_ERR_BAD_INPUT if an id is outside [0, n_verts) or a tag is not 0/1
+ * (map is then unspecified). */
+agc_status agc_aggregate(agc_context* ctx, int32_t n_verts, int64_t n_edges,
+                         const int32_t* edges, const uint8_t* tags,
+                         int32_t* map, int32_t* n_coarse);
+
+/* ---------------------------------------------------- (b) coarse system */
+
+/* Galerkin coarse system (Sec. 4.1 "Algebraic Coarsening and System
+ * Assembly"; supplement Sec. 2): A_c = P^T H P with H = sum_e S_e^T H_e S_e,
+ * and g_c = P^T g.  Every 3x3 fine block (i, j) moves to (map i, map j) and
+ * equal keys are summed in a fixed order (sorted keys, segmented reduction),
+ * so results are bitwise reproducible.  The upper triangle is reduced and
+ * mirrored, so A_c is exactly symmetric.
+ *   elem_H   : [n_elems][144] row-major 12x12 blocks, DoF order 3a+k, of
+ *              type h_dtype (AGC_F64 or AGC_F32); each must be symmetric.
+ *   g        : [n_verts][3] float64, may be NULL (then g_c is not written).
+ *   map      : [n_verts] int32 in [0, n_coarse) with every label used, as
+ *              produced by agc_aggregate.
+ *   out_dtype: AGC_F64 (sums in float64) or AGC_F32 (sums and storage in
+ *              float32).
+ *   A_c      : [host] out, a new matrix owned by the caller, freed with
+ *              agc_matrix_destroy.
+ *   g_c      : [n_coarse][3] float64 out, may be NULL. */
+agc_status agc_assemble_coarse(agc_context* ctx, const agc_mesh* mesh,
+                               const void* elem_H, int32_t h_dtype,
+                               const double* g, const int32_t* map, int32_t n_coarse,
+                               int32_t out_dtype, agc_matrix** A_c, double* g_c);
+
+/* The fine matrix H itself (map = identity), the comparator of the method. */
+agc_status agc_assemble_fine(agc_context* ctx, const agc_mesh* mesh,
+                             const void* elem_H, int32_t h_dtype, int32_t out_dtype,
+                             agc_matrix** H);
+
+agc_status agc_matrix_destroy(agc_context* ctx, agc_matrix* A);
+/* [host] n_rows (block rows), nnzb (stored 3x3 blocks), dtype. */
+agc_status agc_matrix_info(const agc_matrix* A, int32_t* n_rows, int64_t* nnzb, int32_t* dtype);
+/* Copies the BSR arrays into caller buffers:
+ *   row_ptr [n_rows+1] int32, col_idx [nnzb] int32 (sorted within a row),
+ *   vals    [nnzb][9] row-major 3x3 blocks of the matrix dtype.
+ * Any pointer may be NULL to skip that array. */
+agc_status agc_matrix_copy(agc_context* ctx, const agc_matrix* A, int32_t* row_ptr,
+                           int32_t* col_idx, void* vals);
+/* y = A x on [n_rows][3] float64 vectors (float32 matrices are read as
+ * float32 and multiplied in float64). */
+agc_status agc_spmv(agc_context* ctx, const agc_matrix* A, const double* x, double* y);
+
+/* --------------------------------------------------------- (c) PCG solve */
+
+typedef struct {
+  int32_t iters;    /* PCG iterations performed                          */
+  double rel_res;   /* ||b - A x||_2 / ||b||_2 of the recurrence residual */
+} agc_pcg_info;
+
+/* 3x3 block-Jacobi preconditioned conjugate gradients (Alg. overview, solve
+ * step; Sec. 5.1 "Preconditioners") on A x = b, A symmetric positive
+ * definite.  x holds the initial guess on entry (zeros for the standard
+ * start) and the result on exit.  Stops when the recurrence residual
+ * satisfies ||r||_2 <= rtol ||b||_2 or after max_iter iterations
+ * (AGC_ERR_NOT_CONVERGED, x = last iterate).  Vectors and inner products are
+ * float64 for both matrix dtypes.  info may be NULL.  Synchronises. */
+agc_status agc_pcg(agc_context* ctx, const agc_matrix* A, const double* b, double* x,
+                   double rtol, int32_t max_iter, agc_pcg_info* info);
+
+/* -------------------------------------------------- (d) prolongation, P^T */
+
+/* x = P x_c: x[v] = x_c[map[v]] (Sec. 4.3; d_f = U^T d_c).  Bitwise copy. */
+agc_status agc_prolongate(agc_context* ctx, int32_t n_verts, const int32_t* map,
+                          int32_t n_coarse, const double* x_c, double* x);
+/* v_c = P^T v: v_c[c] = sum of v over the members of c, summed in a fixed
+ * order (Sec. 4.1, g_c = sum over child(c) of g_f). */
+agc_status agc_restrict(agc_context* ctx, int32_t n_verts, const int32_t* map,
+                        int32_t n_coarse, const double* v, double* v_c);
+
+/* ----------------------------------------------------------- all in one */
+
+typedef struct {
+  const agc_mesh* mesh;    /* from agc_mesh_create                             */
+  int64_t n_edges;         /* edge list for the aggregation                    */
+  const int32_t* edges;    /* [n_edges][2] int32                               */
+  const uint8_t* tags;     /* [n_edges] uint8                                  */
+  const double* elem_H;    /* [n_elems][144] float64 element blocks            */
+  const float* elem_H32;   /* optional float32 copy of elem_H for the mixed
+                              inner assembly (NULL: convert elem_H on load)   */
+  const double* g;         /* [n_verts][3] float64 gradient                    */
+} agc_problem;
+
+typedef struct {
+  int32_t precision;   /* AGC_PREC_FP64, or AGC_PREC_MIXED: float32 assembly,
+                          storage and SpMV values; float64 vectors, inner
+                          products, residuals and iterative refinement       */
+  int32_t coarsen;     /* 1: aggregate by tags; 0: fine solve (map = identity) */
+  double rtol;         /* target ||b_c - A_c x_c||_2 / ||b_c||_2 in float64    */
+  int32_t max_iter;    /* PCG iteration cap (over all refinement steps)        */
+  double inner_rtol;   /* mixed: relative tolerance of each inner PCG solve    */
+  int32_t max_refine;  /* mixed: cap on refinement steps                       */
+  int32_t timing;      /* 1: fill the ms_* fields of agc_solve_info            */
+} agc_solve_opts;
+
+typedef struct {
+  int32_t n_coarse;    /* super-nodes (n_verts when coarsen = 0)               */
+  int64_t nnzb;        /* stored blocks of the solved matrix                   */
+  int32_t pcg_iters;   /* PCG iterations over all refinement steps             */
+  int32_t refine_iters;/* refinement steps (0 for AGC_PREC_FP64)               */
+  double rel_res;      /* final float64 relative residual of the coarse system */
+  float ms_aggregate, ms_assemble, ms_pcg, ms_prolong;  /* when timing = 1    */
+} agc_solve_info;
+
+/* One Newton linear solve, steps in the order of Alg. overview (mapping,
+ * coarse assembly, coarse solve, prolongation): x = P A_c^{-1} P^T g.
+ *   x       : [n_verts][3] float64 out.
+ *   map_out : [n_verts] int32 out, may be NULL.
+ *   info    : [host] out, may be NULL.  Synchronises. */
+agc_status agc_solve(agc_context* ctx, const agc_problem* prob, const agc_solve_opts* opts,
+                     double* x, int32_t* map_out, agc_solve_info* info);
+
+/* Derivatives of L(x) for x = agc_solve(...) given w = dL/dx:
+ *   lambda_c = A_c^{-1} P^T w,  dL/dg = P lambda_c,
+ *   dL/dH_e  = -(S_e P lambda_c)(S_e x)^T   (12x12, not symmetrised).
+ * Only the map (and x) from the forward pass are needed; A_c is assembled
+ * again, never stored.  dg: [n_verts][3] float64 out; dH: [n_elems][144]
+ * float64 out, may be NULL.  opts->precision selects the solve as in
+ * agc_solve.  Synchronises. */
+agc_status agc_solve_backward(agc_context* ctx, const agc_problem* prob,
+                              const agc_solve_opts* opts, const int32_t* map, int32_t n_coarse,
+                              const double* x, const double* w, double* dg, double* dH,
+                              agc_solve_info* info);
+
+/* ------------------------------------------------------------- profiling */
+
+/* Runs agc_spmv `reps` times between two HIP events on the context's stream
+ * and returns the mean time of one launch in *avg_ms [host].  Synchronises. */
+agc_status agc_time_spmv(agc_context* ctx, const agc_matrix* A, const double* x, double* y,
+                         int32_t reps, float* avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AGC_H */

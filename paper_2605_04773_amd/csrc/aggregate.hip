@@ -1,0 +1,189 @@
+// Fine-to-coarse aggregation, restriction and prolongation.
+//
+// Sec. 4.1 and supplement Sec. 1: super-nodes are the connected components of
+// the graph of collapsible edges, and the supplement's elected-lane popcount
+// plus group prefix sum (Alg. 2, Sec. 1.3) orders them by their smallest fine
+// id.  The paper finds components with 32-bit in-warp hash masks applied
+// level by level.  On gfx950 one edge-parallel pass of lock-free union-find
+// does the same job for any component size: a root is only ever hooked below
+// a smaller root, so the surviving root of every component is its smallest
+// vertex whatever the order of the races.  Flagging the roots and an
+// exclusive scan then give exactly the canonical labels.
+#include "segreduce.h"
+
+namespace agc {
+
+__device__ __forceinline__ int32_t ld_parent(const int32_t* p, int32_t v) { return load_agent(p + v); }
+
+__device__ __forceinline__ void st_parent(int32_t* p, int32_t v, int32_t x) {
+  __hip_atomic_store(p + v, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of v with path shortening.  Invariant: parent[x] <= x, roots satisfy
+// parent[x] == x, and a value written is always an ancestor of the node.
+__device__ int32_t find_root(int32_t* parent, int32_t v) {
+  int32_t cur = ld_parent(parent, v);
+  if (cur != v) {
+    int32_t prev = v, nxt;
+    while (cur > (nxt = ld_parent(parent, cur))) {
+      st_parent(parent, prev, nxt);
+      prev = cur;
+      cur = nxt;
+    }
+  }
+  return cur;
+}
+
+__global__ void k_cc_init(int32_t* __restrict__ parent, int32_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    parent[v] = (int32_t)v;
+}
+
+__global__ void k_cc_hook(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
+                          int32_t* parent, int32_t n, unsigned* err) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = edges[2 * e], v = edges[2 * e + 1];
+    const uint8_t t = tags[e];
+    if (u < 0 || u >= n || v < 0 || v >= n) {
+      atomicOr(err, kErrRange);
+      continue;
+    }
+    if (t > 1) {
+      atomicOr(err, kErrTag);
+      continue;
+    }
+    if (t == 0 || u == v) continue;
+    int32_t ru = find_root(parent, u), rv = find_root(parent, v);
+    while (ru != rv) {
+      const int32_t lo = ru < rv ? ru : rv, hi = ru < rv ? rv : ru;
+      const int32_t old = atomicCAS(parent + hi, hi, lo);
+      if (old == hi) break;                       // hooked hi below lo
+      // hi stopped being a root meanwhile: continue from its new root
+      const int32_t r = find_root(parent, old);
+      if (ru == hi) ru = r; else rv = r;
+    }
+  }
+}
+
+__global__ void k_cc_compress(int32_t* parent, int32_t n, uint32_t* __restrict__ flag) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = find_root(parent, (int32_t)v);
+    flag[v] = (r == (int32_t)v) ? 1u : 0u;
+  }
+}
+
+__global__ void k_cc_label(const int32_t* __restrict__ parent, const uint32_t* __restrict__ rank, int32_t n,
+                           int32_t* __restrict__ map) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t x = (int32_t)v, p;
+    while ((p = parent[x]) != x) x = p;       // read-only walk to the root
+    map[v] = (int32_t)rank[x];
+  }
+}
+
+static unsigned gs_blocks(int64_t n) {
+  int64_t b = (n + kWG - 1) / kWG;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags, int32_t* map) {
+  if (n == 0) return 0;
+  int32_t* parent = c->ws.get<int32_t>("agg.parent", n);
+  uint32_t* flag = c->ws.get<uint32_t>("agg.flag", n + 1);
+  err_reset(c);
+  k_cc_init<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
+  AGC_LAUNCH_CHECK();
+  if (m > 0) {
+    k_cc_hook<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n, c->d_err);
+    AGC_LAUNCH_CHECK();
+  }
+  k_cc_compress<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n, flag);
+  AGC_LAUNCH_CHECK();
+  scan_u32(c, flag, flag, n, "agg.scan");
+  k_cc_label<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, flag, n, map);
+  AGC_LAUNCH_CHECK();
+  uint32_t nc = 0;
+  AGC_HIP(hipMemcpyAsync(&nc, flag + n, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  err_throw(err_fetch(c));
+  return (int32_t)nc;
+}
+
+// ------------------------------------------------------------- members
+
+__global__ void k_members_init(const int32_t* __restrict__ map, int32_t n, int32_t n_c, uint32_t* __restrict__ k,
+                               uint32_t* __restrict__ v, unsigned* err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = map[i];
+    if (c < 0 || c >= n_c) atomicOr(err, kErrMap);
+    k[i] = (uint32_t)(c < 0 ? 0 : (c >= n_c ? n_c - 1 : c));
+    v[i] = (uint32_t)i;
+  }
+}
+
+void group_members(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, uint32_t* members,
+                   uint32_t* mkeys) {
+  uint32_t* k2 = c->ws.get<uint32_t>("mem.k2", n);
+  uint32_t* v2 = c->ws.get<uint32_t>("mem.v2", n);
+  err_reset(c);
+  k_members_init<<<gs_blocks(n), kWG, 0, c->stream>>>(map, n, n_c, mkeys, members, c->d_err);
+  AGC_LAUNCH_CHECK();
+  const bool alt = radix_sort_u32(c, mkeys, members, k2, v2, n, bits_for((uint64_t)(n_c > 0 ? n_c - 1 : 0)),
+                                  "mem.sort");
+  if (alt) {
+    AGC_HIP(hipMemcpyAsync(mkeys, k2, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
+    AGC_HIP(hipMemcpyAsync(members, v2, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
+  }
+}
+
+struct RestrictOp {
+  const uint32_t* members;
+  const double* v;
+  const double* sub;
+  double* out;
+  __device__ void load(int64_t k, double x[3]) const {
+    const int64_t i = members[k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) x[r] = sub ? v[3 * i + r] - sub[3 * i + r] : v[3 * i + r];
+  }
+  __device__ void store(int64_t s, const double x[3]) const {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) out[3 * s + r] = x[r];
+  }
+  __device__ void add(int64_t s, const double x[3]) const {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) out[3 * s + r] += x[r];
+  }
+};
+
+// members/mkeys from group_members; every coarse id has at least one member,
+// so segment s is coarse node s.
+void restrict_sorted(agc_context* c, int32_t n, int32_t n_c, const uint32_t* members, const uint32_t* mkeys,
+                     const double* v, const double* sub, double* v_c) {
+  (void)n_c;
+  RestrictOp op{members, v, sub, v_c};
+  seg_reduce<3, double, uint32_t, RestrictOp>(c, mkeys, n, op, (uint32_t*)nullptr, false, "rst.seg");
+}
+
+__global__ void k_prolong(const int32_t* __restrict__ map, int32_t n, int32_t n_c, const double* __restrict__ xc,
+                          double* __restrict__ x, unsigned* err) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cc = map[v];
+    if (cc < 0 || cc >= n_c) {
+      atomicOr(err, kErrMap);
+      x[3 * v] = x[3 * v + 1] = x[3 * v + 2] = 0.0;
+      continue;
+    }
+    x[3 * v] = xc[3 * cc];
+    x[3 * v + 1] = xc[3 * cc + 1];
+    x[3 * v + 2] = xc[3 * cc + 2];
+  }
+}
+
+void prolongate(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, const double* xc, double* x) {
+  if (n == 0) return;
+  k_prolong<<<gs_blocks(n), kWG, 0, c->stream>>>(map, n, n_c, xc, x, c->d_err);
+  AGC_LAUNCH_CHECK();
+}
+
+}  // namespace agc

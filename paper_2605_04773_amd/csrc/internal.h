@@ -1,0 +1,130 @@
+// Internal interfaces of libagc (not part of the ABI).
+#pragma once
+
+#include "common.h"
+
+namespace agc {
+
+// A BSR 3x3 matrix with full symmetric storage.  vals holds 9 planes:
+// vals[(3r+s)*nnzb + k] is entry (r, s) of block k, so the nine loads of one
+// block by consecutive lanes are each contiguous.  rowidx[k] is the block row
+// of block k (used by the nonzero-balanced SpMV); diag[r] the position of the
+// diagonal block of row r.
+struct Matrix {
+  int32_t n = 0;
+  int64_t nnzb = 0;
+  int32_t dtype = AGC_F64;
+  DevBuf row_ptr, col, rowidx, diag, vals;
+  int32_t* rp() const { return (int32_t*)row_ptr.p; }
+  int32_t* ci() const { return (int32_t*)col.p; }
+  int32_t* ri() const { return (int32_t*)rowidx.p; }
+  int32_t* dg() const { return (int32_t*)diag.p; }
+  void reserve(int32_t n_rows, int64_t nb, int32_t dt) {
+    n = n_rows;
+    nnzb = nb;
+    dtype = dt;
+    row_ptr.ensure(sizeof(int32_t) * (size_t)(n_rows + 1));
+    col.ensure(sizeof(int32_t) * (size_t)(nb + 1));
+    rowidx.ensure(sizeof(int32_t) * (size_t)(nb + 1));
+    diag.ensure(sizeof(int32_t) * (size_t)(n_rows + 1));
+    vals.ensure((dt == AGC_F64 ? 8 : 4) * 9 * (size_t)(nb + 1));
+  }
+  void release() {
+    row_ptr.release(); col.release(); rowidx.release(); diag.release(); vals.release();
+  }
+};
+
+// Static structure of a mesh.
+struct Mesh {
+  int32_t n_verts = 0;
+  int64_t n_elems = 0;
+  DevBuf elem_verts;     // private copy, [n_elems][4]
+  // fine upper pattern (row <= col), sorted by (row, col)
+  int64_t nf = 0;
+  DevBuf fu_row, fu_col;
+  DevBuf plan_ptr;       // [nf+1] into plan
+  DevBuf plan;           // [10 n_elems]: e*16 + a*4 + b, sub-block (a,b) of H_e
+  // full fine pattern from the upper one
+  int64_t ff_nnzb = 0;
+  DevBuf ff_row_ptr, ff_col, ff_rowidx, ff_src, ff_diag;   // src = upper*2 + transposed
+  // vertex -> (element, local vertex) incidence
+  DevBuf va_ptr, va;     // va[k] = e*4 + a
+  void release() {
+    elem_verts.release(); fu_row.release(); fu_col.release(); plan_ptr.release(); plan.release();
+    ff_row_ptr.release(); ff_col.release(); ff_rowidx.release(); ff_src.release(); ff_diag.release();
+    va_ptr.release(); va.release();
+  }
+};
+
+// Device PCG scalars.
+struct PcgState {
+  double rz, pq, alpha, beta, rr, bb, tol2;
+  int32_t iter, max_iter, done;   // done: 0 running, 1 converged, 2 max_iter, 3 breakdown
+  uint32_t ticket_a, ticket_b, ticket_c;
+  int32_t pad;
+};
+
+// ----------------------------------------------------------- primitives
+// out[0..n] = exclusive scan of in[0..n), out[n] = total.  out may equal in.
+void scan_u32(agc_context* c, const uint32_t* in, uint32_t* out, int64_t n, const std::string& tag);
+// Stable LSD radix sort of (key, val) pairs on bits [0, nbits).  Returns true
+// when the result ended in the *_alt arrays.
+bool radix_sort_u64(agc_context* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                    uint32_t* vals_alt, int64_t n, int nbits, const std::string& tag);
+bool radix_sort_u32(agc_context* c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                    uint32_t* vals_alt, int64_t n, int nbits, const std::string& tag);
+
+// error word helpers
+void err_reset(agc_context* c);
+unsigned err_fetch(agc_context* c);   // synchronises
+void err_throw(unsigned bits);        // throws on a nonzero word
+
+// ------------------------------------------------------------ aggregation
+int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags,
+                  int32_t* map);
+// members[k]: vertices sorted by (map, id); mkeys[k] = map[members[k]]
+void group_members(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, uint32_t* members,
+                   uint32_t* mkeys);
+// v_c[c] = sum over members of v (fixed order); sub != nullptr gives (v - sub)
+void restrict_sorted(agc_context* c, int32_t n, int32_t n_c, const uint32_t* members,
+                     const uint32_t* mkeys, const double* v, const double* sub, double* v_c);
+// x[v] = x_c[map[v]]; a map value outside [0, n_c) sets kErrMap and writes 0
+void prolongate(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, const double* x_c, double* x);
+
+// ------------------------------------------------------------- assembly
+void mesh_build(agc_context* c, Mesh& m, int32_t n_verts, int64_t n_elems, const int32_t* ev);
+void assemble_fine(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
+                   int32_t out_dtype, Matrix& out);
+void assemble_coarse(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
+                     const int32_t* map, int32_t n_c, int32_t out_dtype, Matrix& out);
+// rf = g - H (P x_c) on the fine level from float64 element blocks (map may be null: identity)
+void elem_residual(agc_context* c, const Mesh& m, const double* elem_h, const int32_t* map,
+                   const double* x_c, const double* g, double* rf);
+// dH_e = -(dg_e)(x_e)^T
+void elem_outer(agc_context* c, const Mesh& m, const double* dg, const double* x, double* dh);
+
+// ------------------------------------------------------------------ PCG
+void spmv(agc_context* c, const Matrix& a, const double* x, double* y);
+// returns status (AGC_OK / NOT_CONVERGED / NOT_SPD); *iters, *rel set
+int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol, int32_t max_iter,
+        int32_t* iters, double* rel);
+// ||v||_2 of an [n][3] vector (float64, fixed order); synchronises
+double norm2(agc_context* c, const double* v, int64_t n3, const std::string& tag);
+void axpy_vec(agc_context* c, double* y, const double* x, double a, int64_t n3);
+
+}  // namespace agc
+
+// --------------------------------------------------------------- context
+struct agc_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  agc::Workspace ws;
+  unsigned* d_err = nullptr;   // device error word for the current call
+  unsigned* h_err = nullptr;   // pinned host mirror
+  void* d_pcg = nullptr;       // device PCG state (agc::PcgState)
+  void* h_pcg = nullptr;       // pinned host mirror
+  hipEvent_t ev[8] = {};
+  agc::Matrix solve_a;         // matrices reused across agc_solve calls
+  agc::Matrix solve_a64;
+};
