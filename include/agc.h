@@ -182,7 +182,8 @@ typedef struct {
   int64_t n_edges;         /* edge list for the aggregation                    */
   const int32_t* edges;    /* [n_edges][2] int32                               */
   const uint8_t* tags;     /* [n_edges] uint8                                  */
-  const double* elem_H;    /* [n_elems][144] float64 element blocks            */
+  const double* elem_H;    /* [n_elems][144] float64 element blocks, 16-byte
+                              aligned (AGC_ERR_INVALID_ARG otherwise)         */
   const float* elem_H32;   /* optional float32 copy of elem_H for the mixed
                               inner assembly (NULL: convert elem_H on load)   */
   const double* g;         /* [n_verts][3] float64 gradient                    */
@@ -197,7 +198,9 @@ typedef struct {
   int32_t max_iter;    /* PCG iteration cap (over all refinement steps)        */
   double inner_rtol;   /* mixed: relative tolerance of each inner PCG solve    */
   int32_t max_refine;  /* mixed: cap on refinement steps                       */
-  int32_t timing;      /* 1: fill the ms_* fields of agc_solve_info            */
+  int32_t timing;      /* 1: fill the ms_* phase times of agc_solve_info;
+                          2: also time every PCG SpMV launch with HIP events
+                          (spmv_launches, ms_spmv)                            */
 } agc_solve_opts;
 
 typedef struct {
@@ -206,7 +209,9 @@ typedef struct {
   int32_t pcg_iters;   /* PCG iterations over all refinement steps             */
   int32_t refine_iters;/* refinement steps (0 for AGC_PREC_FP64)               */
   double rel_res;      /* final float64 relative residual of the coarse system */
-  float ms_aggregate, ms_assemble, ms_pcg, ms_prolong;  /* when timing = 1    */
+  float ms_aggregate, ms_assemble, ms_pcg, ms_prolong;  /* when timing >= 1   */
+  int32_t spmv_launches;  /* when timing = 2: PCG SpMV launches that did work  */
+  float ms_spmv;          /* when timing = 2: their summed duration            */
 } agc_solve_info;
 
 /* One Newton linear solve, steps in the order of Alg. overview (mapping,

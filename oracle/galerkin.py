@@ -50,6 +50,27 @@ def fine_hessian(n_verts: int, elem_verts, elem_H, chunk: int = 1 << 16) -> sp.c
     return total
 
 
+def fine_matvec(elem_verts, elem_H, x, chunk: int = 1 << 18) -> np.ndarray:
+    """H x = sum_e S_e^T (H_e (S_e x)) element by element, x of shape (n, 3)."""
+    x = np.asarray(x, dtype=np.float64)
+    ev = np.asarray(elem_verts, dtype=np.int64)
+    hv = np.asarray(elem_H).reshape(-1, 12, 12)
+    y = np.zeros(x.shape[0] * 3)
+    for s in range(0, ev.shape[0], chunk):
+        e = ev[s:s + chunk]
+        ye = np.einsum("nij,nj->ni", hv[s:s + chunk].astype(np.float64), x[e].reshape(-1, 12))
+        dofs = (3 * e[:, :, None] + np.arange(3)[None, None, :]).reshape(-1)
+        y += np.bincount(dofs, weights=ye.reshape(-1), minlength=y.shape[0])
+    return y.reshape(-1, 3)
+
+
+def coarse_residual(elem_verts, elem_H, g, map_, n_c, x_c) -> np.ndarray:
+    """b_c - A_c x_c = P^T (g - H P x_c) without assembling anything."""
+    m = np.asarray(map_, dtype=np.int64)
+    x = np.asarray(x_c, dtype=np.float64).reshape(-1, 3)[m]
+    return restrict(m, n_c, np.asarray(g, dtype=np.float64) - fine_matvec(elem_verts, elem_H, x))
+
+
 def coarse_system(n_verts: int, elem_verts, elem_H, g, map_, n_c):
     """A_c = P^T H P (sparse) and b_c = P^T g, shape (n_c, 3)."""
     p = prolongation(map_, n_c)
@@ -77,6 +98,34 @@ def coarse_pattern(elem_verts, map_, n_c):
     c = np.tile(m, (1, 4)).ravel()
     key = np.unique(r * n_c + c)
     return key // n_c, key % n_c
+
+
+def coarse_rows(elem_verts, elem_H, map_, n_c, rows):
+    """Selected block rows of A_c straight from the elements (for systems too big to assemble whole).
+
+    Returns {(r, c): 3x3 block} for r in rows: the sum over every element e and
+    local pair (a, b) with map(v_a) = r of the sub-block H_e[a, b] at column map(v_b).
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    m = np.asarray(map_, dtype=np.int64)[np.asarray(elem_verts, dtype=np.int64)]       # (n_e, 4)
+    want = np.zeros(n_c, dtype=bool)
+    want[rows] = True
+    sel = np.nonzero(want[m].any(axis=1))[0]
+    he = np.asarray(elem_H, dtype=np.float64).reshape(-1, 4, 3, 4, 3)[sel]           # [e, a, i, b, j]
+    ms = m[sel]
+    out = {}
+    for a in range(4):
+        ra = ms[:, a]
+        keep = want[ra]
+        for b in range(4):
+            key = ra[keep] * n_c + ms[keep, b]
+            blocks = he[keep, a, :, b, :]
+            uk, inv = np.unique(key, return_inverse=True)
+            acc = np.zeros((uk.shape[0], 3, 3))
+            np.add.at(acc, inv, blocks)
+            for k, blk in zip(uk.tolist(), acc):
+                out[(k // n_c, k % n_c)] = out.get((k // n_c, k % n_c), 0.0) + blk
+    return out
 
 
 def to_blocks(a: sp.spmatrix, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:

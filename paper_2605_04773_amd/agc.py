@@ -66,7 +66,7 @@ class agc_solve_opts(ctypes.Structure):
 class agc_solve_info(ctypes.Structure):
     _fields_ = [("n_coarse", c_int32), ("nnzb", c_int64), ("pcg_iters", c_int32), ("refine_iters", c_int32),
                 ("rel_res", c_double), ("ms_aggregate", c_float), ("ms_assemble", c_float),
-                ("ms_pcg", c_float), ("ms_prolong", c_float)]
+                ("ms_pcg", c_float), ("ms_prolong", c_float), ("spmv_launches", c_int32), ("ms_spmv", c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

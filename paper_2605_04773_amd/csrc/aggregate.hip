@@ -13,7 +13,12 @@
 
 namespace agc {
 
-__device__ __forceinline__ int32_t ld_parent(const int32_t* p, int32_t v) { return load_agent(p + v); }
+// Plain (cached) loads: a stale value read from this XCD's cache is still an
+// ancestor of the node (parents only ever move towards smaller ids), so a
+// walk that starts from it still ends at a root, and the compare-and-swap
+// that hooks a root works on the device-coherent value and reports the
+// current one when it fails.
+__device__ __forceinline__ int32_t ld_parent(const int32_t* p, int32_t v) { return p[v]; }
 
 __device__ __forceinline__ void st_parent(int32_t* p, int32_t v, int32_t x) {
   __hip_atomic_store(p + v, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -96,6 +96,7 @@ void validate_opts(const agc_solve_opts* o) {
 void validate_problem(const agc_problem* p) {
   AGC_REQUIRE(p && p->mesh, "problem or mesh is null");
   AGC_REQUIRE(p->elem_H && p->g, "elem_H and g are required");
+  AGC_REQUIRE(((uintptr_t)p->elem_H & 15) == 0, "elem_H must be 16-byte aligned");
   AGC_REQUIRE(p->n_edges >= 0, "n_edges < 0");
 }
 
@@ -221,6 +222,7 @@ agc_status agc_create(agc_context** out, int32_t device, void* stream) {
     AGC_HIP(hipMalloc(&c->d_pcg, sizeof(agc::PcgState)));
     AGC_HIP(hipHostMalloc(&c->h_pcg, sizeof(agc::PcgState), hipHostMallocDefault));
     for (auto& e : c->ev) AGC_HIP(hipEventCreate(&e));
+    for (auto& e : c->kev) AGC_HIP(hipEventCreate(&e));
   } catch (const Error& e) {
     agc_destroy(c);
     return e.code;
@@ -248,6 +250,8 @@ agc_status agc_destroy(agc_context* c) {
   if (c->d_pcg) (void)hipFree(c->d_pcg);
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->kev)
     if (e) (void)hipEventDestroy(e);
   delete c;
   return AGC_OK;
@@ -472,6 +476,9 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   const int32_t n = mesh.n_verts;
   AGC_REQUIRE(o->coarsen == 0 || p->n_edges == 0 || (p->edges && p->tags), "edges/tags null");
   Timer tm(c, o->timing != 0);
+  c->kernel_timing = o->timing >= 2;
+  c->spmv_ms = 0.0;
+  c->spmv_n = 0;
   tm.mark();                                                   // 0
   Restrictor R{c, n, n, nullptr, nullptr, nullptr};
   int32_t* map = nullptr;
@@ -498,6 +505,7 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   }
   tm.mark();                                                   // 4
   AGC_HIP(hipStreamSynchronize(c->stream));
+  c->kernel_timing = false;
   if (info) {
     info->n_coarse = R.n_c;
     info->nnzb = res.nnzb;
@@ -508,6 +516,8 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
     info->ms_assemble = tm.ms(1, 2);
     info->ms_pcg = tm.ms(2, 3);
     info->ms_prolong = tm.ms(3, 4);
+    info->spmv_launches = (int32_t)c->spmv_n;
+    info->ms_spmv = (float)c->spmv_ms;
   }
   API_END(c)
 }

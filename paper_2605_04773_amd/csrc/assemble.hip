@@ -111,21 +111,31 @@ __global__ void k_split_keys(const uint64_t* __restrict__ ukeys, int64_t nu, uin
 
 // ------------------------------------------------ full symmetric pattern
 
-__global__ void k_count_upper(const int32_t* __restrict__ ur, const int32_t* __restrict__ uc, int64_t nu,
-                              uint32_t* __restrict__ cnt_up, uint32_t* __restrict__ cnt_low,
-                              uint32_t* __restrict__ cnt_col) {
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += (int64_t)gridDim.x * blockDim.x) {
-    const int r = ur[u], c = uc[u];
-    atomicAdd(&cnt_up[r], 1u);
-    atomicAdd(&cnt_col[c], 1u);
-    if (r != c) atomicAdd(&cnt_low[c], 1u);
+// start[k] = first position whose key is >= k, for k in [0, n_keys], over
+// ascending keys; empty keys get empty ranges.  One coalesced pass, no atomics.
+template <class K>
+__global__ void k_key_starts(const K* __restrict__ keys, int64_t m, int64_t n_keys, uint32_t* __restrict__ start) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = (int64_t)keys[i];
+    const int64_t prev = (i == 0) ? -1 : (int64_t)keys[i - 1];
+    for (int64_t j = prev + 1; j <= k; ++j) start[j] = (uint32_t)i;
+    if (i == m - 1)
+      for (int64_t j = k + 1; j <= n_keys; ++j) start[j] = (uint32_t)m;
   }
 }
 
-__global__ void k_add_u32(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
-                          uint32_t* __restrict__ out, int64_t n) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-    out[k] = a[k] + b[k];
+// per row r: upper count (row r), lower count (column r above the diagonal),
+// full row length.  The diagonal entry of column r is the last in CSC order.
+__global__ void k_full_counts(const uint32_t* __restrict__ up_start, const uint32_t* __restrict__ col_start,
+                              const uint32_t* __restrict__ csc_u, const int32_t* __restrict__ ur, int32_t n,
+                              uint32_t* __restrict__ cnt_low, uint32_t* __restrict__ len) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t cup = up_start[r + 1] - up_start[r];
+    const uint32_t c0 = col_start[r], c1 = col_start[r + 1];
+    const uint32_t has_diag = (c1 > c0 && ur[csc_u[c1 - 1]] == (int32_t)r) ? 1u : 0u;
+    cnt_low[r] = c1 - c0 - has_diag;
+    len[r] = cup + (c1 - c0 - has_diag);
+  }
 }
 
 // upper entries: position after the row's lower part
@@ -183,30 +193,13 @@ struct FullPattern {
 
 static int64_t build_full(agc_context* c, int32_t n, int64_t nu, const int32_t* ur, const int32_t* uc,
                           FullPattern out, const std::string& tag) {
-  uint32_t* cnt_up = c->ws.get<uint32_t>(tag + ".cup", n + 1);
+  AGC_REQUIRE(nu >= 1, "empty pattern");
   uint32_t* cnt_low = c->ws.get<uint32_t>(tag + ".clow", n + 1);
-  uint32_t* cnt_col = c->ws.get<uint32_t>(tag + ".ccol", n + 1);
   uint32_t* up_start = c->ws.get<uint32_t>(tag + ".ups", n + 1);
   uint32_t* col_start = c->ws.get<uint32_t>(tag + ".cols", n + 1);
   uint32_t* rp = c->ws.get<uint32_t>(tag + ".rp", n + 1);
   const unsigned gn = grid_stride_blocks(n + 1), gu = grid_stride_blocks(nu);
-  k_zero_u32<<<gn, kWG, 0, c->stream>>>(cnt_up, n + 1);
-  k_zero_u32<<<gn, kWG, 0, c->stream>>>(cnt_low, n + 1);
-  k_zero_u32<<<gn, kWG, 0, c->stream>>>(cnt_col, n + 1);
-  AGC_LAUNCH_CHECK();
-  k_count_upper<<<gu, kWG, 0, c->stream>>>(ur, uc, nu, cnt_up, cnt_low, cnt_col);
-  AGC_LAUNCH_CHECK();
-  k_add_u32<<<gn, kWG, 0, c->stream>>>(cnt_up, cnt_low, rp, n);
-  AGC_LAUNCH_CHECK();
-  scan_u32(c, rp, rp, n, tag + ".s1");
-  scan_u32(c, cnt_up, up_start, n, tag + ".s2");
-  scan_u32(c, cnt_col, col_start, n, tag + ".s3");
-  k_fill_i32<<<gn, kWG, 0, c->stream>>>(out.diag, n, -1);
-  AGC_LAUNCH_CHECK();
-  k_place_upper<<<gu, kWG, 0, c->stream>>>(ur, uc, nu, rp, cnt_low, up_start, out.col, out.rowidx, out.src,
-                                           out.diag);
-  AGC_LAUNCH_CHECK();
-  // stable sort of upper entries by column
+  // stable sort of the upper entries by column: CSC order, by row inside a column
   uint32_t* kc = c->ws.get<uint32_t>(tag + ".kc", nu);
   uint32_t* kc2 = c->ws.get<uint32_t>(tag + ".kc2", nu);
   uint32_t* vu = c->ws.get<uint32_t>(tag + ".vu", nu);
@@ -216,6 +209,18 @@ static int64_t build_full(agc_context* c, int32_t n, int64_t nu, const int32_t* 
   AGC_LAUNCH_CHECK();
   const bool alt = radix_sort_u32(c, kc, vu, kc2, vu2, nu, bits_for((uint64_t)(n > 0 ? n - 1 : 0)), tag + ".sort");
   const uint32_t* csc_u = alt ? vu2 : vu;
+  const uint32_t* csc_key = alt ? kc2 : kc;
+  // row starts of the upper entries and column starts of the CSC order
+  k_key_starts<int32_t><<<gu, kWG, 0, c->stream>>>(ur, nu, n, up_start);
+  k_key_starts<uint32_t><<<gu, kWG, 0, c->stream>>>(csc_key, nu, n, col_start);
+  k_full_counts<<<gn, kWG, 0, c->stream>>>(up_start, col_start, csc_u, ur, n, cnt_low, rp);
+  AGC_LAUNCH_CHECK();
+  scan_u32(c, rp, rp, n, tag + ".s1");
+  k_fill_i32<<<gn, kWG, 0, c->stream>>>(out.diag, n, -1);
+  AGC_LAUNCH_CHECK();
+  k_place_upper<<<gu, kWG, 0, c->stream>>>(ur, uc, nu, rp, cnt_low, up_start, out.col, out.rowidx, out.src,
+                                           out.diag);
+  AGC_LAUNCH_CHECK();
   k_place_lower<<<gu, kWG, 0, c->stream>>>(csc_u, nu, ur, uc, col_start, rp, out.col, out.rowidx, out.src);
   AGC_LAUNCH_CHECK();
   k_u32_to_i32<<<gn, kWG, 0, c->stream>>>(rp, out.row_ptr, n + 1);
@@ -515,30 +520,45 @@ void assemble_coarse(agc_context* c, const Mesh& m, const void* eh, int32_t h_dt
 
 // --------------------------------------------- matrix-free float64 residual
 
-// rf[v] = g[v] - sum over incident (e, a) of H_e[a, :] (P x_c)_e, float64.
-__global__ __launch_bounds__(kWG) void k_elem_residual(const double* __restrict__ eh, const int32_t* __restrict__ ev,
-                                                       const uint32_t* __restrict__ vptr,
-                                                       const uint32_t* __restrict__ va, const int32_t* __restrict__ map,
-                                                       const double* __restrict__ xc, const double* __restrict__ g,
+// ye[12 e + i] = row i of H_e times (P x_c) restricted to element e.  One
+// thread per (element, row): consecutive threads stream consecutive 96-byte
+// rows of the element blocks, so every byte of elem_H is read once.
+__global__ __launch_bounds__(kWG) void k_elem_rows(const double* __restrict__ eh, const int32_t* __restrict__ ev,
+                                                   int64_t ne, const int32_t* __restrict__ map,
+                                                   const double* __restrict__ xc, double* __restrict__ ye) {
+  const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (t >= 12 * ne) return;
+  const int64_t e = t / 12;
+  const double2* h = reinterpret_cast<const double2*>(eh + 12 * t);   // row t of the stacked blocks
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int u = ev[4 * e + b];
+    const int64_t cu = 3 * (int64_t)(map ? map[u] : u);
+    const double2 h01 = h[(3 * b) / 2 + 0];
+    const double2 h23 = h[(3 * b) / 2 + 1];
+    // row entries 3b, 3b+1, 3b+2 of the 12 (pairs are 16-byte aligned)
+    double c0, c1, c2;
+    if ((b & 1) == 0) { c0 = h01.x; c1 = h01.y; c2 = h23.x; }
+    else { c0 = h01.y; c1 = h23.x; c2 = h23.y; }
+    acc += c0 * xc[cu] + c1 * xc[cu + 1] + c2 * xc[cu + 2];
+  }
+  ye[t] = acc;
+}
+
+// rf[v] = g[v] - sum over incident (e, a) of ye[12 e + 3 a + r], fixed order.
+__global__ __launch_bounds__(kWG) void k_vert_residual(const double* __restrict__ ye, const uint32_t* __restrict__ vptr,
+                                                       const uint32_t* __restrict__ va, const double* __restrict__ g,
                                                        int32_t n, double* __restrict__ rf) {
   const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (v >= n) return;
   double acc[3] = {0.0, 0.0, 0.0};
   const uint32_t k0 = vptr[v], k1 = vptr[v + 1];
   for (uint32_t k = k0; k < k1; ++k) {
-    const uint32_t code = va[k];
-    const int64_t e = code >> 2;
-    const int a = code & 3;
-    const double* h = eh + e * 144 + (3 * a) * 12;
+    const uint32_t code = va[k];            // e*4 + a
+    const double* y = ye + 3 * (int64_t)code;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int u = ev[4 * e + b];
-      const int cu = map ? map[u] : u;
-      const double x0 = xc[3 * (int64_t)cu], x1 = xc[3 * (int64_t)cu + 1], x2 = xc[3 * (int64_t)cu + 2];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-        acc[r] += h[r * 12 + 3 * b] * x0 + h[r * 12 + 3 * b + 1] * x1 + h[r * 12 + 3 * b + 2] * x2;
-    }
+    for (int r = 0; r < 3; ++r) acc[r] += y[r];
   }
 #pragma unroll
   for (int r = 0; r < 3; ++r) rf[3 * v + r] = g[3 * v + r] - acc[r];
@@ -546,9 +566,12 @@ __global__ __launch_bounds__(kWG) void k_elem_residual(const double* __restrict_
 
 void elem_residual(agc_context* c, const Mesh& m, const double* eh, const int32_t* map, const double* xc,
                    const double* g, double* rf) {
-  k_elem_residual<<<blocks_for(m.n_verts, kWG), kWG, 0, c->stream>>>(
-      eh, (const int32_t*)m.elem_verts.p, (const uint32_t*)m.va_ptr.p, (const uint32_t*)m.va.p, map, xc, g,
-      m.n_verts, rf);
+  double* ye = c->ws.get<double>("res.ye", 12 * m.n_elems);
+  k_elem_rows<<<blocks_for(12 * m.n_elems, kWG), kWG, 0, c->stream>>>(eh, (const int32_t*)m.elem_verts.p,
+                                                                      m.n_elems, map, xc, ye);
+  AGC_LAUNCH_CHECK();
+  k_vert_residual<<<blocks_for(m.n_verts, kWG), kWG, 0, c->stream>>>(ye, (const uint32_t*)m.va_ptr.p,
+                                                                     (const uint32_t*)m.va.p, g, m.n_verts, rf);
   AGC_LAUNCH_CHECK();
 }
 

@@ -56,6 +56,8 @@ struct Mesh {
   }
 };
 
+constexpr int kMaxChunk = 256;   // PCG iterations enqueued between two host checks
+
 // Device PCG scalars.
 struct PcgState {
   double rz, pq, alpha, beta, rr, bb, tol2;
@@ -125,6 +127,10 @@ struct agc_context {
   void* d_pcg = nullptr;       // device PCG state (agc::PcgState)
   void* h_pcg = nullptr;       // pinned host mirror
   hipEvent_t ev[8] = {};
+  hipEvent_t kev[2 * agc::kMaxChunk] = {};   // per-launch events for kernel timing
+  bool kernel_timing = false;
+  double spmv_ms = 0.0;                      // summed duration of timed SpMV launches
+  int64_t spmv_n = 0;
   agc::Matrix solve_a;         // matrices reused across agc_solve calls
   agc::Matrix solve_a64;
 };

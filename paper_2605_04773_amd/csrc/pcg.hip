@@ -242,18 +242,25 @@ __global__ __launch_bounds__(kWG) void k_jacobi(const int32_t* __restrict__ diag
 
 // ------------------------------------------------------------------ PCG
 
-// Last-workgroup-done reduction: every workgroup stores its partial(s); the
-// workgroup that takes the final ticket sums all partials in index order.
+// Last-workgroup-done reduction: thread 0 of every workgroup publishes its
+// partial(s) with a device-coherent store, waits until the store has
+// completed, then takes a ticket; the workgroup that takes the final ticket
+// reads all partials with device-coherent loads and sums them in index
+// order.  A device-scope fence would do the same job but on gfx950 it writes
+// back and invalidates the whole L2 of the XCD, once per workgroup.
+__device__ __forceinline__ void publish(double* part, int64_t i, double v) {
+  __hip_atomic_store(part + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ bool take_last(uint32_t* ticket, unsigned n_groups) {
   __shared__ bool is_last;
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t t = atomicAdd(ticket, 1u);
+    __builtin_amdgcn_s_waitcnt(0);   // thread 0's published partials have completed
+    const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (t == n_groups - 1);
   }
   __syncthreads();
-  if (is_last) __threadfence();   // acquire: the other workgroups' partials are visible
   return is_last;
 }
 
@@ -261,6 +268,52 @@ __device__ __forceinline__ double sum_partials(const double* part, unsigned n, d
   double s = 0.0;
   for (unsigned i = threadIdx.x; i < n; i += kWG) s += load_agent(part + i);
   return wg_sum(s, red);
+}
+
+// Two-level version for grids of thousands of workgroups: a single ticket
+// counter would serialise one device-scope atomic per workgroup.  Workgroups
+// are grouped by kTicketGroup; the last of each group sums its group's
+// partials and takes a ticket on the top counter; the last of those sums the
+// group sums.  All sums run in index order.  K values per workgroup, valid in
+// thread 0 on entry; on return true, tot[] is valid in thread 0.
+constexpr unsigned kTicketGroup = 128;
+// Counters sit 256 bytes apart: atomics that share a cache line are
+// serialised at the same cache slice even when their addresses differ.
+constexpr unsigned kTicketStride = 64;
+
+struct Tickets {
+  uint32_t* group;   // [n_groups * kTicketStride], zero between launches
+  uint32_t* top;     // [1], zero between launches, on a line of its own
+  double* part;      // [K][G]
+  double* gpart;     // [K][n_groups]
+};
+
+template <int K>
+__device__ bool reduce_last(const double (&v)[K], const Tickets& tk, double* red, double (&tot)[K]) {
+  __shared__ bool flag;
+  const unsigned G = gridDim.x, b = blockIdx.x, g = b / kTicketGroup;
+  const unsigned NG = (G + kTicketGroup - 1) / kTicketGroup;
+  const unsigned g0 = g * kTicketGroup;
+  const unsigned gsize = (G - g0 < kTicketGroup) ? G - g0 : kTicketGroup;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) publish(tk.part, (int64_t)k * G + b, v[k]);
+  }
+  if (!take_last(tk.group + g * kTicketStride, gsize)) return false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = (threadIdx.x < gsize) ? load_agent(tk.part + (int64_t)k * G + g0 + threadIdx.x) : 0.0;
+    s = wg_sum(s, red);
+    if (threadIdx.x == 0) publish(tk.gpart, (int64_t)k * NG + g, s);
+  }
+  if (threadIdx.x == 0)
+    __hip_atomic_store(tk.group + g * kTicketStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!take_last(tk.top, NG)) return false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) tot[k] = sum_partials(tk.gpart + (int64_t)k * NG, NG, red);
+  if (threadIdx.x == 0) __hip_atomic_store(tk.top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  (void)flag;
+  return true;
 }
 
 __device__ __forceinline__ void dinv_apply(const double* __restrict__ dinv, int64_t n, int64_t r, const double v[3],
@@ -277,8 +330,7 @@ __device__ __forceinline__ void dinv_apply(const double* __restrict__ dinv, int6
 __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, const double* __restrict__ q,
                                                   const double* __restrict__ dinv, int32_t n, double* __restrict__ r,
                                                   double* __restrict__ z, double* __restrict__ p,
-                                                  double* __restrict__ part, PcgState* st, double rtol,
-                                                  int32_t max_iter) {
+                                                  Tickets tk, PcgState* st, double rtol, int32_t max_iter) {
   __shared__ double red[kWaves];
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   double rz = 0.0, rr = 0.0, bb = 0.0;
@@ -300,19 +352,10 @@ __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, 
       rr += rv[k] * rv[k];
     }
   }
-  const unsigned G = gridDim.x;
-  rz = wg_sum(rz, red);
-  rr = wg_sum(rr, red);
-  bb = wg_sum(bb, red);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = rz;
-    part[G + blockIdx.x] = rr;
-    part[2 * G + blockIdx.x] = bb;
-  }
-  if (!take_last(&st->ticket_b, G)) return;
-  const double trz = sum_partials(part, G, red);
-  const double trr = sum_partials(part + G, G, red);
-  const double tbb = sum_partials(part + 2 * G, G, red);
+  const double v[3] = {wg_sum(rz, red), wg_sum(rr, red), wg_sum(bb, red)};
+  double tot[3];
+  if (!reduce_last<3>(v, tk, red, tot)) return;
+  const double trz = tot[0], trr = tot[1], tbb = tot[2];
   if (threadIdx.x == 0) {
     st->rz = trz;
     st->rr = trr;
@@ -335,15 +378,14 @@ template <class T>
 __global__ __launch_bounds__(kWG) void k_pcg_a(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const int32_t* __restrict__ ri, const T* __restrict__ vals,
                                                int64_t nnzb, const double* __restrict__ p, double* __restrict__ q,
-                                               double* __restrict__ carry, double* __restrict__ part, PcgState* st) {
+                                               double* __restrict__ carry, Tickets tk, PcgState* st) {
   __shared__ double red[kWaves];
   if (st->done) return;
-  const double d = spmv_tile<T>(rp, col, ri, vals, nnzb, p, q, carry, p, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = d;
-  if (!take_last(&st->ticket_a, gridDim.x)) return;
-  const double pq = sum_partials(part, gridDim.x, red);
+  const double v[1] = {spmv_tile<T>(rp, col, ri, vals, nnzb, p, q, carry, p, red)};
+  double tot[1];
+  if (!reduce_last<1>(v, tk, red, tot)) return;
+  const double pq = tot[0];
   if (threadIdx.x == 0) {
-    st->ticket_a = 0;
     st->pq = pq;
     if (pq > 0.0 && pq == pq) st->alpha = st->rz / pq;
     else st->done = 3;
@@ -354,7 +396,7 @@ __global__ __launch_bounds__(kWG) void k_pcg_b(const int32_t* __restrict__ rp, i
                                                const double* __restrict__ qy, const double* __restrict__ carry,
                                                const double* __restrict__ dinv, const double* __restrict__ p,
                                                double* __restrict__ x, double* __restrict__ r,
-                                               double* __restrict__ z, double* __restrict__ part, PcgState* st) {
+                                               double* __restrict__ z, Tickets tk, PcgState* st) {
   __shared__ double red[kWaves];
   if (st->done) return;
   const double alpha = st->alpha;
@@ -377,18 +419,11 @@ __global__ __launch_bounds__(kWG) void k_pcg_b(const int32_t* __restrict__ rp, i
       rr += rv[k] * rv[k];
     }
   }
-  const unsigned G = gridDim.x;
-  rz = wg_sum(rz, red);
-  rr = wg_sum(rr, red);
+  const double v[2] = {wg_sum(rz, red), wg_sum(rr, red)};
+  double tot[2];
+  if (!reduce_last<2>(v, tk, red, tot)) return;
+  const double trz = tot[0], trr = tot[1];
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = rz;
-    part[G + blockIdx.x] = rr;
-  }
-  if (!take_last(&st->ticket_b, G)) return;
-  const double trz = sum_partials(part, G, red);
-  const double trr = sum_partials(part + G, G, red);
-  if (threadIdx.x == 0) {
-    st->ticket_b = 0;
     st->beta = trz / st->rz;
     st->rz = trz;
     st->rr = trr;
@@ -421,44 +456,81 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   double* q = c->ws.get<double>("pcg.q", n3);
   const unsigned gr = blocks_for(n, kWG);
   const unsigned gs = blocks_for(a.nnzb, kSpmvTile);
-  double* part = c->ws.get<double>("pcg.part", 3 * (int64_t)(gr > gs ? gr : gs) + 3);
+  const unsigned gmax = gr > gs ? gr : gs;
+  const unsigned ngmax = (gmax + kTicketGroup - 1) / kTicketGroup;
+  // one ticket state serves the three kernels: they run one after another and
+  // every counter is back at zero when a kernel ends
+  const int64_t ncnt = (int64_t)(ngmax + 1) * kTicketStride;
+  uint32_t* cnt = c->ws.get<uint32_t>("pcg.tickets", ncnt);
+  Tickets tk{cnt, cnt + (int64_t)ngmax * kTicketStride, c->ws.get<double>("pcg.part", 3 * (int64_t)gmax),
+             c->ws.get<double>("pcg.gpart", 3 * (int64_t)ngmax)};
   double* carry = spmv_carry(c, a);
   PcgState* st = (PcgState*)c->d_pcg;
   PcgState* hs = (PcgState*)c->h_pcg;
 
   err_reset(c);
   AGC_HIP(hipMemsetAsync(st, 0, sizeof(PcgState), c->stream));
+  AGC_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * ncnt, c->stream));
   if (a.dtype == AGC_F64)
     k_jacobi<double><<<gr, kWG, 0, c->stream>>>(a.dg(), (const double*)a.vals.p, a.nnzb, n, dinv, c->d_err);
   else
     k_jacobi<float><<<gr, kWG, 0, c->stream>>>(a.dg(), (const float*)a.vals.p, a.nnzb, n, dinv, c->d_err);
   AGC_LAUNCH_CHECK();
   spmv(c, a, x, q);   // q = A x0
-  k_pcg_init<<<gr, kWG, 0, c->stream>>>(b, q, dinv, n, r, z, p, part, st, rtol, max_iter);
+  k_pcg_init<<<gr, kWG, 0, c->stream>>>(b, q, dinv, n, r, z, p, tk, st, rtol, max_iter);
   AGC_LAUNCH_CHECK();
   if (err_fetch(c)) return AGC_ERR_NOT_SPD;
 
-  int chunk = 4;
-  int64_t launched = 0;
+  // The host enqueues iterations in chunks and reads the device scalars in
+  // between.  The chunk length is the number of iterations the residual's
+  // observed geometric decay still needs, so few launches land after
+  // convergence (those return at once).
+  const bool kt = c->kernel_timing;
+  int chunk = 8;
+  int64_t launched = 0, chunk_start = 0;
+  int prev_it = -1;
+  double prev_rr = 0.0;
   for (;;) {
     AGC_HIP(hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
     AGC_HIP(hipStreamSynchronize(c->stream));
+    if (kt) {
+      // SpMV launches that did work: global index < completed iterations
+      for (int64_t j = chunk_start; j < launched && j < hs->iter; ++j) {
+        float ms = 0.f;
+        const int s = (int)(j - chunk_start);
+        AGC_HIP(hipEventElapsedTime(&ms, c->kev[2 * s], c->kev[2 * s + 1]));
+        c->spmv_ms += ms;
+        c->spmv_n += 1;
+      }
+    }
     if (hs->done) break;
     // the device stops at max_iter; this only guards the host against a lost state
     if (launched > (int64_t)max_iter + 64) throw Error(AGC_ERR_DEVICE, "PCG state did not advance");
+    if (prev_it >= 0 && hs->iter > prev_it && hs->rr > 0.0 && hs->rr < prev_rr) {
+      const double rate = log(hs->rr / prev_rr) / (double)(hs->iter - prev_it);
+      const double remaining = log(hs->tol2 / hs->rr) / rate;
+      chunk = remaining < 2.0 ? 2 : (remaining > 256.0 ? 256 : (int)ceil(remaining));
+    } else if (prev_it >= 0) {
+      chunk = chunk < 32 ? 2 * chunk : 64;
+    }
+    if (chunk > kMaxChunk) chunk = kMaxChunk;
+    prev_it = hs->iter;
+    prev_rr = hs->rr;
+    chunk_start = launched;
     launched += chunk;
     for (int it = 0; it < chunk; ++it) {
+      if (kt) AGC_HIP(hipEventRecord(c->kev[2 * it], c->stream));
       if (a.dtype == AGC_F64)
         k_pcg_a<double><<<gs, kWG, 0, c->stream>>>(a.rp(), a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, p, q,
-                                                   carry, part, st);
+                                                   carry, tk, st);
       else
         k_pcg_a<float><<<gs, kWG, 0, c->stream>>>(a.rp(), a.ci(), a.ri(), (const float*)a.vals.p, a.nnzb, p, q,
-                                                  carry, part, st);
-      k_pcg_b<<<gr, kWG, 0, c->stream>>>(a.rp(), n, q, carry, dinv, p, x, r, z, part, st);
+                                                  carry, tk, st);
+      if (kt) AGC_HIP(hipEventRecord(c->kev[2 * it + 1], c->stream));
+      k_pcg_b<<<gr, kWG, 0, c->stream>>>(a.rp(), n, q, carry, dinv, p, x, r, z, tk, st);
       k_pcg_c<<<blocks_for(n3, kWG), kWG, 0, c->stream>>>(n3, z, p, st);
     }
     AGC_LAUNCH_CHECK();
-    if (chunk < 32) chunk *= 2;
   }
   *iters = hs->iter;
   if (hs->bb == 0.0) {

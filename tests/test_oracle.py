@@ -162,6 +162,33 @@ def test_coarse_pattern(c1):
     assert brute == key
 
 
+def test_coarse_rows_match_full_product(c1):
+    m, n_c = aggregate.components(c1["n_verts"], c1["edges"], c1["tags"])
+    a_c, _ = galerkin.coarse_system(c1["n_verts"], c1["elem_verts"], c1["elem_H"], c1["g"], m, n_c)
+    ad = a_c.toarray()
+    rows = [0, 1, n_c // 2, n_c - 1]
+    blocks = galerkin.coarse_rows(c1["elem_verts"], c1["elem_H"], m, n_c, rows)
+    pr, pc = galerkin.coarse_pattern(c1["elem_verts"], m, n_c)
+    assert set(blocks) == {(r, c) for r, c in zip(pr.tolist(), pc.tolist()) if r in rows}
+    for (r, c), blk in blocks.items():
+        ref = ad[3 * r:3 * r + 3, 3 * c:3 * c + 3]
+        assert np.allclose(blk, ref, rtol=0, atol=1e-9 * np.abs(ad).max())
+
+
+def test_matrix_free_residual(c1):
+    m, n_c = aggregate.components(c1["n_verts"], c1["edges"], c1["tags"])
+    a_c, b_c = galerkin.coarse_system(c1["n_verts"], c1["elem_verts"], c1["elem_H"], c1["g"], m, n_c)
+    rng = np.random.default_rng(4)
+    x_c = rng.standard_normal((n_c, 3))
+    r = galerkin.coarse_residual(c1["elem_verts"], c1["elem_H"], c1["g"], m, n_c, x_c)
+    ref = b_c.reshape(-1) - a_c @ x_c.reshape(-1)
+    assert np.allclose(r.reshape(-1), ref, rtol=0, atol=1e-9 * np.abs(a_c).max() * np.abs(x_c).max())
+    h = galerkin.fine_hessian(c1["n_verts"], c1["elem_verts"], c1["elem_H"])
+    xf = rng.standard_normal((c1["n_verts"], 3))
+    assert np.allclose(galerkin.fine_matvec(c1["elem_verts"], c1["elem_H"], xf).reshape(-1), h @ xf.reshape(-1),
+                       rtol=0, atol=1e-9 * np.abs(h).max() * np.abs(xf).max())
+
+
 def test_all_collapsible_closed_form(c1):
     n = c1["n_verts"]
     m, n_c = aggregate.components(n, c1["edges"], np.ones_like(c1["tags"]))
