@@ -82,7 +82,7 @@ def main():
     # (measured against FP64 references solved to 1e-12; both are reported)
     ap.add_argument("--rtol", type=float, default=4e-7, help="coarsened solve tolerance")
     ap.add_argument("--rtol-fine", type=float, default=1e-6, help="fine FP64 comparator tolerance")
-    ap.add_argument("--inner-rtol", type=float, default=1e-3, help="mixed: tolerance of each inner solve")
+    ap.add_argument("--inner-rtol", type=float, default=1e-4, help="mixed: tolerance of each inner solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the fine and FP64 comparators")
     args = ap.parse_args()

@@ -130,7 +130,8 @@ agc_status agc_assemble_coarse(agc_context* ctx, const agc_mesh* mesh,
                                const double* g, const int32_t* map, int32_t n_coarse,
                                int32_t out_dtype, agc_matrix** A_c, double* g_c);
 
-/* The fine matrix H itself (map = identity), the comparator of the method. */
+/* The fine matrix H itself (map = identity), the comparator of the method.
+ * It shares the mesh's static block pattern: destroy it before the mesh. */
 agc_status agc_assemble_fine(agc_context* ctx, const agc_mesh* mesh,
                              const void* elem_H, int32_t h_dtype, int32_t out_dtype,
                              agc_matrix** H);

@@ -322,7 +322,7 @@ def agc_restrict(ctx: Context, map_: torch.Tensor, n_coarse: int, v: torch.Tenso
     return out
 
 
-def make_opts(precision=AGC_PREC_FP64, coarsen=1, rtol=1e-10, max_iter=20000, inner_rtol=1e-3, max_refine=20,
+def make_opts(precision=AGC_PREC_FP64, coarsen=1, rtol=1e-10, max_iter=20000, inner_rtol=1e-4, max_refine=20,
               timing=0) -> agc_solve_opts:
     return agc_solve_opts(int(precision), int(coarsen), float(rtol), int(max_iter), float(inner_rtol),
                           int(max_refine), int(timing))

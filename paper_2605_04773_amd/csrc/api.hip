@@ -45,10 +45,10 @@ __global__ void k_iota_i32(int32_t* __restrict__ v, int32_t n) {
 }
 
 template <class T>
-__global__ void k_planes_to_aos(const T* __restrict__ planes, int64_t nnzb, T* __restrict__ out) {
+__global__ void k_planes_to_aos(const T* __restrict__ planes, int64_t nnzb, int64_t stride, T* __restrict__ out) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnzb; k += (int64_t)gridDim.x * blockDim.x)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[9 * k + i] = planes[(int64_t)i * nnzb + k];
+    for (int i = 0; i < 9; ++i) out[9 * k + i] = planes[(int64_t)i * stride + k];
 }
 
 unsigned gsb(int64_t n) {
@@ -389,9 +389,11 @@ agc_status agc_matrix_copy(agc_context* c, const agc_matrix* a, int32_t* row_ptr
     AGC_HIP(hipMemcpyAsync(col_idx, m.ci(), sizeof(int32_t) * m.nnzb, hipMemcpyDeviceToDevice, c->stream));
   if (vals && m.nnzb) {
     if (m.dtype == AGC_F64)
-      k_planes_to_aos<double><<<gsb(m.nnzb), agc::kWG, 0, c->stream>>>((const double*)m.vals.p, m.nnzb, (double*)vals);
+      k_planes_to_aos<double><<<gsb(m.nnzb), agc::kWG, 0, c->stream>>>((const double*)m.vals.p, m.nnzb, m.stride,
+                                                                       (double*)vals);
     else
-      k_planes_to_aos<float><<<gsb(m.nnzb), agc::kWG, 0, c->stream>>>((const float*)m.vals.p, m.nnzb, (float*)vals);
+      k_planes_to_aos<float><<<gsb(m.nnzb), agc::kWG, 0, c->stream>>>((const float*)m.vals.p, m.nnzb, m.stride,
+                                                                      (float*)vals);
     AGC_LAUNCH_CHECK();
   }
   AGC_HIP(hipStreamSynchronize(c->stream));

@@ -349,11 +349,12 @@ __global__ __launch_bounds__(kWG) void k_fine_gather(const In* __restrict__ eh, 
   for (int i = 0; i < 9; ++i) F[(int64_t)i * nf + f] = acc[i];
 }
 
-// Full matrix values from upper blocks U (planes of stride us) and src.
+// Full matrix values (planes of stride vs) from upper blocks U (planes of
+// stride us) and src.
 template <class Acc>
 __global__ __launch_bounds__(kWG) void k_fill_vals(const uint32_t* __restrict__ src, int64_t nnz,
                                                    const Acc* __restrict__ U, int64_t us,
-                                                   Acc* __restrict__ vals) {
+                                                   Acc* __restrict__ vals, int64_t vs) {
   const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (p >= nnz) return;
   const uint32_t s = src[p];
@@ -362,10 +363,10 @@ __global__ __launch_bounds__(kWG) void k_fill_vals(const uint32_t* __restrict__ 
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) vals[(int64_t)(3 * r + q) * nnz + p] = U[(int64_t)(3 * q + r) * us + u];
+      for (int q = 0; q < 3; ++q) vals[(int64_t)(3 * r + q) * vs + p] = U[(int64_t)(3 * q + r) * us + u];
   } else {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) vals[(int64_t)i * nnz + p] = U[(int64_t)i * us + u];
+    for (int i = 0; i < 9; ++i) vals[(int64_t)i * vs + p] = U[(int64_t)i * us + u];
   }
 }
 
@@ -384,29 +385,22 @@ static Acc* fine_upper(agc_context* c, const Mesh& m, const void* eh, int32_t h_
   return F;
 }
 
-static void copy_pattern(agc_context* c, Matrix& out, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
-                         const int32_t* ri, const int32_t* dg) {
-  AGC_HIP(hipMemcpyAsync(out.rp(), rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, c->stream));
-  AGC_HIP(hipMemcpyAsync(out.ci(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, c->stream));
-  AGC_HIP(hipMemcpyAsync(out.ri(), ri, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, c->stream));
-  AGC_HIP(hipMemcpyAsync(out.dg(), dg, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c->stream));
-}
-
+// The fine matrix borrows the mesh's static pattern (no copy per assembly).
 void assemble_fine(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, int32_t out_dtype,
                    Matrix& out) {
   const int32_t n = m.n_verts;
   const int64_t nnz = m.ff_nnzb;
-  out.reserve(n, nnz, out_dtype);
-  copy_pattern(c, out, n, nnz, (const int32_t*)m.ff_row_ptr.p, (const int32_t*)m.ff_col.p,
-               (const int32_t*)m.ff_rowidx.p, (const int32_t*)m.ff_diag.p);
+  out.reserve_values(n, nnz, out_dtype);
+  out.borrow_pattern((const int32_t*)m.ff_row_ptr.p, (const int32_t*)m.ff_col.p, (const int32_t*)m.ff_rowidx.p,
+                     (const int32_t*)m.ff_diag.p);
   if (out_dtype == AGC_F64) {
     double* F = fine_upper<double>(c, m, eh, h_dtype);
     k_fill_vals<double><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>((const uint32_t*)m.ff_src.p, nnz, F, m.nf,
-                                                                    (double*)out.vals.p);
+                                                                    (double*)out.vals.p, out.stride);
   } else {
     float* F = fine_upper<float>(c, m, eh, h_dtype);
     k_fill_vals<float><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>((const uint32_t*)m.ff_src.p, nnz, F, m.nf,
-                                                                   (float*)out.vals.p);
+                                                                   (float*)out.vals.p, out.stride);
   }
   AGC_LAUNCH_CHECK();
 }
@@ -506,8 +500,8 @@ static void coarse_impl(agc_context* c, const Mesh& m, const void* eh, int32_t h
   int32_t nnz = 0;
   AGC_HIP(hipMemcpyAsync(&nnz, out.rp() + n_c, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   err_throw(err_fetch(c));
-  out.nnzb = nnz;   // plane stride of vals
-  k_fill_vals<Acc><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>(src, nnz, U, nf, (Acc*)out.vals.p);
+  out.set_nnzb(nnz);
+  k_fill_vals<Acc><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>(src, nnz, U, nf, (Acc*)out.vals.p, out.stride);
   AGC_LAUNCH_CHECK();
 }
 

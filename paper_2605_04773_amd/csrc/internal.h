@@ -6,31 +6,53 @@
 namespace agc {
 
 // A BSR 3x3 matrix with full symmetric storage.  vals holds 9 planes:
-// vals[(3r+s)*nnzb + k] is entry (r, s) of block k, so the nine loads of one
-// block by consecutive lanes are each contiguous.  rowidx[k] is the block row
-// of block k (used by the nonzero-balanced SpMV); diag[r] the position of the
-// diagonal block of row r.
+// vals[(3r+s)*stride + k] is entry (r, s) of block k, so the nine loads of one
+// block by consecutive lanes are each contiguous; stride is nnzb rounded up to
+// a multiple of 64 so that every plane starts 256-byte aligned.  rowidx[k] is
+// the block row of block k (used by the nonzero-balanced SpMV); diag[r] the
+// position of the diagonal block of row r.
+inline int64_t plane_stride(int64_t nnzb) { return (nnzb + 63) / 64 * 64; }
+
 struct Matrix {
   int32_t n = 0;
   int64_t nnzb = 0;
+  int64_t stride = 0;
   int32_t dtype = AGC_F64;
   DevBuf row_ptr, col, rowidx, diag, vals;
-  int32_t* rp() const { return (int32_t*)row_ptr.p; }
-  int32_t* ci() const { return (int32_t*)col.p; }
-  int32_t* ri() const { return (int32_t*)rowidx.p; }
-  int32_t* dg() const { return (int32_t*)diag.p; }
+  // a matrix may borrow a static pattern (the fine matrix uses its mesh's)
+  const int32_t *ext_rp = nullptr, *ext_ci = nullptr, *ext_ri = nullptr, *ext_dg = nullptr;
+  int32_t* rp() const { return ext_rp ? (int32_t*)ext_rp : (int32_t*)row_ptr.p; }
+  int32_t* ci() const { return ext_ci ? (int32_t*)ext_ci : (int32_t*)col.p; }
+  int32_t* ri() const { return ext_ri ? (int32_t*)ext_ri : (int32_t*)rowidx.p; }
+  int32_t* dg() const { return ext_dg ? (int32_t*)ext_dg : (int32_t*)diag.p; }
+  // capacity for up to nb blocks; set_nnzb fixes the final count and stride
   void reserve(int32_t n_rows, int64_t nb, int32_t dt) {
-    n = n_rows;
-    nnzb = nb;
-    dtype = dt;
+    ext_rp = ext_ci = ext_ri = ext_dg = nullptr;
     row_ptr.ensure(sizeof(int32_t) * (size_t)(n_rows + 1));
-    col.ensure(sizeof(int32_t) * (size_t)(nb + 1));
-    rowidx.ensure(sizeof(int32_t) * (size_t)(nb + 1));
+    col.ensure(sizeof(int32_t) * (size_t)(plane_stride(nb) + 4));
+    rowidx.ensure(sizeof(int32_t) * (size_t)(plane_stride(nb) + 4));
     diag.ensure(sizeof(int32_t) * (size_t)(n_rows + 1));
-    vals.ensure((dt == AGC_F64 ? 8 : 4) * 9 * (size_t)(nb + 1));
+    reserve_values(n_rows, nb, dt);
+  }
+  void reserve_values(int32_t n_rows, int64_t nb, int32_t dt) {
+    n = n_rows;
+    dtype = dt;
+    vals.ensure((dt == AGC_F64 ? 8 : 4) * 9 * (size_t)(plane_stride(nb) + 4));
+    set_nnzb(nb);
+  }
+  void borrow_pattern(const int32_t* rp_, const int32_t* ci_, const int32_t* ri_, const int32_t* dg_) {
+    ext_rp = rp_;
+    ext_ci = ci_;
+    ext_ri = ri_;
+    ext_dg = dg_;
+  }
+  void set_nnzb(int64_t nb) {
+    nnzb = nb;
+    stride = plane_stride(nb);
   }
   void release() {
     row_ptr.release(); col.release(); rowidx.release(); diag.release(); vals.release();
+    ext_rp = ext_ci = ext_ri = ext_dg = nullptr;
   }
 };
 
@@ -60,9 +82,9 @@ constexpr int kMaxChunk = 256;   // PCG iterations enqueued between two host che
 
 // Device PCG scalars.
 struct PcgState {
-  double rz, pq, alpha, beta, rr, bb, tol2;
+  double rz_hist[2];              // r^T z of the last even / odd iteration
+  double rr, bb, tol2;
   int32_t iter, max_iter, done;   // done: 0 running, 1 converged, 2 max_iter, 3 breakdown
-  uint32_t ticket_a, ticket_b, ticket_c;
   int32_t pad;
 };
 

@@ -1,34 +1,75 @@
 // BSR 3x3 SpMV and 3x3 block-Jacobi PCG (Alg. overview, solve step;
 // Sec. 5.1 "Preconditioners").
 //
-// SpMV is nonzero-balanced: workgroup w owns blocks [256 w, 256 w + 256), one
-// block per thread, whatever the row lengths.  A coarse matrix has one hub
-// row per giant aggregate (tens of thousands of blocks) next to rows of ~13,
-// so splitting by rows would leave most of the chip idle behind one wave.
-// Values are stored as nine planes, so each of the nine loads of a wave is a
-// contiguous 512 B (float64) or 256 B (float32) read.  A row is summed by a
-// wave64 segmented scan plus a carry across the four waves; a row that
-// crosses workgroups leaves one partial per workgroup in `carry`, and the
-// consumer adds them in workgroup order.  All reductions have a fixed order,
-// so every run gives bitwise identical iterates.
+// SpMV is nonzero-balanced: workgroup w owns blocks [1024 w, 1024 w + 1024),
+// four consecutive blocks per thread, whatever the row lengths.  A coarse
+// matrix has one hub row per giant aggregate (tens of thousands of blocks)
+// next to rows of ~13, so splitting by rows would leave most of the chip
+// idle behind one wave.  Values are stored as nine planes (stride padded to
+// 64 blocks), so a thread's four values of one plane are one 16- or 32-byte
+// load and a wave's loads are contiguous.  Rows are summed inside a thread in
+// order, then across threads by a wave64 segmented scan plus a carry across
+// the four waves; a row that crosses workgroups leaves one partial per
+// workgroup in `carry`, and the consumer adds them in workgroup order.
 //
-// PCG per iteration, three launches:
-//   K_a  q = A p and p^T q            (last workgroup: alpha = r^T z / p^T q)
-//   K_b  x += alpha p, r -= alpha q, z = D^{-1} r, r^T z, r^T r
-//                                     (last workgroup: beta, convergence)
-//   K_c  p = z + beta p
-// The scalars live in device memory; the host looks at them only every few
-// iterations.  Launches after convergence return at once.
+// PCG, two launches per iteration j (plus one tiny check per chunk):
+//   K_a  reduce K_b's partials -> r^T z, r^T r; stop test; beta_j;
+//        p_j = z + beta_j p_{j-1} formed on the fly from z and the previous p
+//        (ping-pong buffers; the thread holding a row's diagonal block stores
+//        p_j for that row); q = A p_j; partial p_j^T q per workgroup.
+//   K_b  reduce K_a's partials -> p_j^T q, alpha_j; x += alpha p_j,
+//        r -= alpha q, z = D^{-1} r; partial r^T z, r^T r per workgroup.
+// No atomics and no fences: every workgroup of a kernel sums all partials
+// of the previous kernel in the same fixed order (the kernel boundary makes
+// them visible), so every workgroup takes the same decisions and every run
+// gives bitwise identical iterates.  The host reads the scalars only
+// between chunks of iterations; launches after convergence return at once.
 #include "internal.h"
 
 namespace agc {
 
-constexpr int kSpmvTile = kWG;   // blocks per workgroup
+constexpr int kItems = 4;
+constexpr int kTile = kWG * kItems;   // blocks per SpMV workgroup
+
+// ------------------------------------------------------------ loads
+
+__device__ __forceinline__ void load4(const int32_t* p, int32_t o[4]) {
+  const int4 v = *reinterpret_cast<const int4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const float* p, double o[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double o[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+
+// The vector the SpMV multiplies: x itself, or p = z + beta p_old.
+struct GatherX {
+  const double* x;
+  __device__ __forceinline__ void get(int64_t c, double o[3]) const {
+    o[0] = x[3 * c];
+    o[1] = x[3 * c + 1];
+    o[2] = x[3 * c + 2];
+  }
+};
+struct GatherP {
+  const double* z;
+  const double* p;
+  double beta;
+  __device__ __forceinline__ void get(int64_t c, double o[3]) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o[i] = z[3 * c + i] + beta * p[3 * c + i];
+  }
+};
 
 // ------------------------------------------------------------- SpMV core
 
-// Segmented (by row) sum of one 3-vector per thread over the workgroup.
-// Returns the run-inclusive sum in v for every thread.
+// Segmented (by key) inclusive sum of one 3-vector per thread over the
+// workgroup, keys non-decreasing in thread order.
 __device__ __forceinline__ void wg_row_scan(int32_t row, double v[3], int32_t* t_row, int* t_single,
                                             double (*t_v)[3]) {
   const unsigned lane = lane_id(), wave = threadIdx.x / kWave;
@@ -62,71 +103,163 @@ __device__ __forceinline__ void wg_row_scan(int32_t row, double v[3], int32_t* t
   }
 }
 
-// One tile of y = A x.  Complete rows go to y; rows crossing the tile edge
-// go to carry[(w*2 + slot)*3 + i] (slot 1: the row starts in this tile,
-// slot 0: it started earlier).  With pdot != nullptr returns, in thread 0,
-// the tile's contribution to pdot^T (A x).
-template <class T>
-__device__ __forceinline__ double spmv_tile(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                            const int32_t* __restrict__ ri, const T* __restrict__ vals,
-                                            int64_t nnzb, const double* __restrict__ x, double* __restrict__ y,
-                                            double* __restrict__ carry, const double* __restrict__ pdot,
-                                            double* red) {
+// One tile of y = A g.  Complete rows go to y; rows crossing the tile edge go
+// to carry[(w*2 + slot)*3 + i] (slot 1: the row starts in this tile, slot 0:
+// it started earlier).  Only the first and the last row of a tile can cross
+// its edges, and the two neighbouring row indices tell which do.
+// PNEW: the thread holding the diagonal block of a row stores the gathered
+// vector of that row to pnew.  DOT: returns, in thread 0, the tile's part of
+// g^T (A g), summed block by block.
+template <class T, class G, bool DOT, bool PNEW>
+__device__ __forceinline__ double spmv_tile(const int32_t* __restrict__ ri, const int32_t* __restrict__ col,
+                                            const T* __restrict__ vals, int64_t nnzb, int64_t stride, const G& g,
+                                            double* __restrict__ y, double* __restrict__ carry,
+                                            double* __restrict__ pnew, double* red) {
   __shared__ int32_t t_row[kWaves];
   __shared__ int t_single[kWaves];
   __shared__ double t_v[kWaves][3];
+  __shared__ int32_t w_row[kWaves];
+  __shared__ double w_s[kWaves][3];
+  __shared__ int32_t edge[2];   // row continuing from the previous tile / into the next one, or -1
   const int64_t w = blockIdx.x;
-  const int64_t k = w * kSpmvTile + threadIdx.x;
-  const bool valid = k < nnzb;
-  int32_t row = INT32_MAX;
-  double v[3] = {0.0, 0.0, 0.0};
-  if (valid) {
-    row = ri[k];
-    const int64_t cx = (int64_t)col[k] * 3;
-    const double x0 = x[cx], x1 = x[cx + 1], x2 = x[cx + 2];
-    double a[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) a[i] = (double)vals[(int64_t)i * nnzb + k];
-    v[0] = a[0] * x0 + a[1] * x1 + a[2] * x2;
-    v[1] = a[3] * x0 + a[4] * x1 + a[5] * x2;
-    v[2] = a[6] * x0 + a[7] * x1 + a[8] * x2;
+  const int64_t t0 = w * kTile;
+  const int64_t t1 = (t0 + kTile < nnzb) ? t0 + kTile : nnzb;
+  const int64_t k0 = t0 + (int64_t)threadIdx.x * kItems;
+  if (threadIdx.x == 0) {
+    const int32_t first = ri[t0];
+    edge[0] = (t0 > 0 && ri[t0 - 1] == first) ? first : -1;
+    const int32_t last = ri[t1 - 1];
+    edge[1] = (t1 < nnzb && ri[t1] == last) ? last : -1;
   }
-  wg_row_scan(row, v, t_row, t_single, t_v);
-  double d = 0.0;
-  if (valid) {
-    const int64_t t0 = w * kSpmvTile;
-    const int64_t t1 = (t0 + kSpmvTile < nnzb) ? t0 + kSpmvTile : nnzb;
-    const bool last = (k == t1 - 1) || (ri[k + 1] != row);
-    if (last) {
-      const int64_t rs = rp[row], re = rp[row + 1];
-      const bool before = rs < t0, after = re > t1;
-      if (!before && !after) {
+  const int64_t kn = k0 + kItems;
+  const int32_t next_row = (kn < t1) ? ri[kn] : INT32_MAX;
+  int32_t r[kItems], c[kItems];
+  double v[kItems][3];
+  double dot = 0.0;
+  if (t0 + kTile <= nnzb) {
+    double a[9][kItems];
+    load4(ri + k0, r);
+    load4(col + k0, c);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) y[3 * (int64_t)row + i] = v[i];
-      } else {
-        const int slot = before ? 0 : 1;
+    for (int i = 0; i < 9; ++i) load4(vals + (int64_t)i * stride + k0, a[i]);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) carry[(w * 2 + slot) * 3 + i] = v[i];
+    for (int j = 0; j < kItems; ++j) {
+      double xv[3];
+      g.get(c[j], xv);
+      v[j][0] = a[0][j] * xv[0] + a[1][j] * xv[1] + a[2][j] * xv[2];
+      v[j][1] = a[3][j] * xv[0] + a[4][j] * xv[1] + a[5][j] * xv[2];
+      v[j][2] = a[6][j] * xv[0] + a[7][j] * xv[1] + a[8][j] * xv[2];
+      if (PNEW && c[j] == r[j]) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) pnew[3 * (int64_t)r[j] + i] = xv[i];
       }
-      if (pdot) d = pdot[3 * (int64_t)row] * v[0] + pdot[3 * (int64_t)row + 1] * v[1] +
-                    pdot[3 * (int64_t)row + 2] * v[2];
+      if (DOT) {
+        double pr[3];
+        g.get(r[j], pr);
+        dot += pr[0] * v[j][0] + pr[1] * v[j][1] + pr[2] * v[j][2];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t k = k0 + j;
+      if (k < nnzb) {
+        r[j] = ri[k];
+        c[j] = col[k];
+        double a[9], xv[3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) a[i] = (double)vals[(int64_t)i * stride + k];
+        g.get(c[j], xv);
+        v[j][0] = a[0] * xv[0] + a[1] * xv[1] + a[2] * xv[2];
+        v[j][1] = a[3] * xv[0] + a[4] * xv[1] + a[5] * xv[2];
+        v[j][2] = a[6] * xv[0] + a[7] * xv[1] + a[8] * xv[2];
+        if (PNEW && c[j] == r[j]) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) pnew[3 * (int64_t)r[j] + i] = xv[i];
+        }
+        if (DOT) {
+          double pr[3];
+          g.get(r[j], pr);
+          dot += pr[0] * v[j][0] + pr[1] * v[j][1] + pr[2] * v[j][2];
+        }
+      } else {
+        r[j] = INT32_MAX;
+        c[j] = 0;
+        v[j][0] = v[j][1] = v[j][2] = 0.0;
+      }
     }
   }
-  if (!pdot) return 0.0;
-  return wg_sum(d, red);
+  // the thread's last run, scanned across threads
+  const int32_t head = r[0], tail = r[kItems - 1];
+  double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < kItems; ++j)
+    if (r[j] == tail) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) s[i] += v[j][i];
+    }
+  wg_row_scan(tail, s, t_row, t_single, t_v);
+  const unsigned lane = lane_id(), wave = threadIdx.x / kWave;
+  int32_t prev_tail = __shfl_up(tail, 1);
+  double prev_s[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) prev_s[i] = __shfl_up(s[i], 1);
+  if (lane == kWave - 1) {
+    w_row[wave] = tail;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) w_s[wave][i] = s[i];
+  }
+  __syncthreads();
+  if (lane == 0) {
+    if (wave > 0) {
+      prev_tail = w_row[wave - 1];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) prev_s[i] = w_s[wave - 1][i];
+    } else {
+      prev_tail = INT32_MIN;
+    }
+  }
+  const int32_t e_before = edge[0], e_after = edge[1];
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (prev_tail == head) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] = prev_s[i];
+  }
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] += v[j][i];
+    const int32_t nr = (j + 1 < kItems) ? r[j + 1] : next_row;
+    if (nr != r[j]) {
+      const int32_t row = r[j];
+      if (row != INT32_MAX) {
+        const bool before = row == e_before, after = row == e_after;
+        if (!before && !after) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) y[3 * (int64_t)row + i] = acc[i];
+        } else {
+          const int slot = before ? 0 : 1;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) carry[(w * 2 + slot) * 3 + i] = acc[i];
+        }
+      }
+      acc[0] = acc[1] = acc[2] = 0.0;
+    }
+  }
+  if (!DOT) return 0.0;
+  return wg_sum(dot, red);
 }
 
 // q[r] for a row whose blocks may span several tiles.
 __device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const double* __restrict__ y,
                                            const double* __restrict__ carry, int64_t r, double q[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q[i] = y[3 * r + i];   // issued with the row pointers; used unless split
   const int64_t rs = rp[r], re = rp[r + 1];
-  const int64_t w0 = rs / kSpmvTile, w1 = (re - 1) / kSpmvTile;
+  const int64_t w0 = rs / kTile, w1 = (re - 1) / kTile;
   if (re <= rs) {
     q[0] = q[1] = q[2] = 0.0;
-  } else if (w0 == w1) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) q[i] = y[3 * r + i];
-  } else {
+  } else if (w0 != w1) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) q[i] = carry[(w0 * 2 + 1) * 3 + i];
     for (int64_t w = w0 + 1; w <= w1; ++w) {
@@ -137,12 +270,12 @@ __device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const
 }
 
 template <class T>
-__global__ __launch_bounds__(kWG) void k_spmv(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                              const int32_t* __restrict__ ri, const T* __restrict__ vals,
-                                              int64_t nnzb, const double* __restrict__ x, double* __restrict__ y,
+__global__ __launch_bounds__(kWG) void k_spmv(const int32_t* __restrict__ col, const int32_t* __restrict__ ri,
+                                              const T* __restrict__ vals, int64_t nnzb, int64_t stride,
+                                              const double* __restrict__ x, double* __restrict__ y,
                                               double* __restrict__ carry) {
   __shared__ double red[kWaves];
-  (void)spmv_tile<T>(rp, col, ri, vals, nnzb, x, y, carry, nullptr, red);
+  (void)spmv_tile<T, GatherX, false, false>(ri, col, vals, nnzb, stride, GatherX{x}, y, carry, nullptr, red);
 }
 
 // rows that cross tiles: y[r] = sum of their partials in tile order
@@ -155,7 +288,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_fix(const int32_t* __restrict__ rp
     y[3 * r] = y[3 * r + 1] = y[3 * r + 2] = 0.0;
     return;
   }
-  if (rs / kSpmvTile == (re - 1) / kSpmvTile) return;
+  if (rs / kTile == (re - 1) / kTile) return;
   double q[3];
   row_result(rp, y, carry, r, q);
 #pragma unroll
@@ -163,20 +296,20 @@ __global__ __launch_bounds__(kWG) void k_spmv_fix(const int32_t* __restrict__ rp
 }
 
 static double* spmv_carry(agc_context* c, const Matrix& a) {
-  const int64_t tiles = (a.nnzb + kSpmvTile - 1) / kSpmvTile;
+  const int64_t tiles = (a.nnzb + kTile - 1) / kTile;
   return c->ws.get<double>("spmv.carry", tiles * 6 + 6);
 }
 
 void spmv(agc_context* c, const Matrix& a, const double* x, double* y) {
   if (a.n == 0) return;
   double* carry = spmv_carry(c, a);
-  const unsigned tiles = blocks_for(a.nnzb, kSpmvTile);
+  const unsigned tiles = blocks_for(a.nnzb, kTile);
   if (a.nnzb > 0) {
     if (a.dtype == AGC_F64)
-      k_spmv<double><<<tiles, kWG, 0, c->stream>>>(a.rp(), a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, x, y,
+      k_spmv<double><<<tiles, kWG, 0, c->stream>>>(a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, a.stride, x, y,
                                                   carry);
     else
-      k_spmv<float><<<tiles, kWG, 0, c->stream>>>(a.rp(), a.ci(), a.ri(), (const float*)a.vals.p, a.nnzb, x, y,
+      k_spmv<float><<<tiles, kWG, 0, c->stream>>>(a.ci(), a.ri(), (const float*)a.vals.p, a.nnzb, a.stride, x, y,
                                                  carry);
     AGC_LAUNCH_CHECK();
   }
@@ -188,7 +321,7 @@ void spmv(agc_context* c, const Matrix& a, const double* x, double* y) {
 
 template <class T>
 __global__ __launch_bounds__(kWG) void k_jacobi(const int32_t* __restrict__ diag, const T* __restrict__ vals,
-                                                int64_t nnzb, int32_t n, double* __restrict__ dinv,
+                                                int64_t stride, int32_t n, double* __restrict__ dinv,
                                                 unsigned* err) {
   const int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (r >= n) return;
@@ -197,7 +330,7 @@ __global__ __launch_bounds__(kWG) void k_jacobi(const int32_t* __restrict__ diag
   bool ok = d >= 0;
   if (ok) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) m[i] = (double)vals[(int64_t)i * nnzb + d];
+    for (int i = 0; i < 9; ++i) m[i] = (double)vals[(int64_t)i * stride + d];
   }
   // Cholesky of the symmetric block (lower triangle read)
   double l00 = 0, l10 = 0, l20 = 0, l11 = 0, l21 = 0, l22 = 0;
@@ -242,78 +375,59 @@ __global__ __launch_bounds__(kWG) void k_jacobi(const int32_t* __restrict__ diag
 
 // ------------------------------------------------------------------ PCG
 
-// Last-workgroup-done reduction: thread 0 of every workgroup publishes its
-// partial(s) with a device-coherent store, waits until the store has
-// completed, then takes a ticket; the workgroup that takes the final ticket
-// reads all partials with device-coherent loads and sums them in index
-// order.  A device-scope fence would do the same job but on gfx950 it writes
-// back and invalidates the whole L2 of the XCD, once per workgroup.
-__device__ __forceinline__ void publish(double* part, int64_t i, double v) {
-  __hip_atomic_store(part + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool take_last(uint32_t* ticket, unsigned n_groups) {
-  __shared__ bool is_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __builtin_amdgcn_s_waitcnt(0);   // thread 0's published partials have completed
-    const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (t == n_groups - 1);
-  }
-  __syncthreads();
-  return is_last;
-}
-
-__device__ __forceinline__ double sum_partials(const double* part, unsigned n, double* red) {
-  double s = 0.0;
-  for (unsigned i = threadIdx.x; i < n; i += kWG) s += load_agent(part + i);
-  return wg_sum(s, red);
-}
-
-// Two-level version for grids of thousands of workgroups: a single ticket
-// counter would serialise one device-scope atomic per workgroup.  Workgroups
-// are grouped by kTicketGroup; the last of each group sums its group's
-// partials and takes a ticket on the top counter; the last of those sums the
-// group sums.  All sums run in index order.  K values per workgroup, valid in
-// thread 0 on entry; on return true, tot[] is valid in thread 0.
-constexpr unsigned kTicketGroup = 128;
-// Counters sit 256 bytes apart: atomics that share a cache line are
-// serialised at the same cache slice even when their addresses differ.
-constexpr unsigned kTicketStride = 64;
-
-struct Tickets {
-  uint32_t* group;   // [n_groups * kTicketStride], zero between launches
-  uint32_t* top;     // [1], zero between launches, on a line of its own
-  double* part;      // [K][G]
-  double* gpart;     // [K][n_groups]
-};
-
+// Sums K rows of per-workgroup partials part[k][0..G) in a fixed order and
+// gives every thread the totals.
 template <int K>
-__device__ bool reduce_last(const double (&v)[K], const Tickets& tk, double* red, double (&tot)[K]) {
-  __shared__ bool flag;
-  const unsigned G = gridDim.x, b = blockIdx.x, g = b / kTicketGroup;
-  const unsigned NG = (G + kTicketGroup - 1) / kTicketGroup;
-  const unsigned g0 = g * kTicketGroup;
-  const unsigned gsize = (G - g0 < kTicketGroup) ? G - g0 : kTicketGroup;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) publish(tk.part, (int64_t)k * G + b, v[k]);
-  }
-  if (!take_last(tk.group + g * kTicketStride, gsize)) return false;
+__device__ __forceinline__ void all_sum(const double* __restrict__ part, unsigned G, double* red, double* bc,
+                                        double (&tot)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    double s = (threadIdx.x < gsize) ? load_agent(tk.part + (int64_t)k * G + g0 + threadIdx.x) : 0.0;
+    double s = 0.0;
+    for (unsigned i = threadIdx.x; i < G; i += kWG) s += part[(int64_t)k * G + i];
     s = wg_sum(s, red);
-    if (threadIdx.x == 0) publish(tk.gpart, (int64_t)k * NG + g, s);
+    if (threadIdx.x == 0) bc[k] = s;
   }
-  if (threadIdx.x == 0)
-    __hip_atomic_store(tk.group + g * kTicketStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!take_last(tk.top, NG)) return false;
+  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < K; ++k) tot[k] = sum_partials(tk.gpart + (int64_t)k * NG, NG, red);
-  if (threadIdx.x == 0) __hip_atomic_store(tk.top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  (void)flag;
-  return true;
+  for (int k = 0; k < K; ++k) tot[k] = bc[k];
+}
+
+// The stop test on the scalars of iteration j (r^T z, r^T r, and at j = 0
+// also b^T b): returns the done code.  Every workgroup computes the same.
+__device__ __forceinline__ int stop_code(int64_t j, double rz, double rr, double bb, double tol2, int32_t max_iter) {
+  if (!(rr == rr) || !(rz == rz)) return 3;
+  if ((j == 0 && bb == 0.0) || rr <= tol2) return 1;
+  if (j >= max_iter) return 2;
+  return 0;
+}
+
+// partials of the update kernels: [3][G_rows] = r^T z, r^T r, b^T b (init only)
+__device__ __forceinline__ void iteration_scalars(int64_t j, const double* pb, unsigned gb, PcgState* st, double rtol,
+                                                  double* red, double* bc, int* done_out, double* rz_out,
+                                                  double* beta_out) {
+  double t[3];
+  all_sum<3>(pb, gb, red, bc, t);
+  const double rz = t[0], rr = t[1];
+  double tol2;
+  if (j == 0) {
+    tol2 = rtol * rtol * t[2];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->bb = t[2];
+      st->tol2 = tol2;
+    }
+  } else {
+    tol2 = st->tol2;
+  }
+  const int done = stop_code(j, rz, rr, t[2], tol2, st->max_iter);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->iter = (int32_t)j;
+    st->rr = rr;
+    st->rz_hist[j & 1] = rz;
+    if (done) st->done = done;
+  }
+  *done_out = done;
+  *rz_out = rz;
+  *beta_out = (j == 0) ? 0.0 : rz / st->rz_hist[(j - 1) & 1];
 }
 
 __device__ __forceinline__ void dinv_apply(const double* __restrict__ dinv, int64_t n, int64_t r, const double v[3],
@@ -326,11 +440,11 @@ __device__ __forceinline__ void dinv_apply(const double* __restrict__ dinv, int6
   z[2] = m[6] * v[0] + m[7] * v[1] + m[8] * v[2];
 }
 
-// r = b - q, z = D^{-1} r, p = z; rz, rr, bb
+// r = b - q, z = D^{-1} r, p_old = 0; partials of r^T z, r^T r, b^T b
 __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, const double* __restrict__ q,
                                                   const double* __restrict__ dinv, int32_t n, double* __restrict__ r,
-                                                  double* __restrict__ z, double* __restrict__ p,
-                                                  Tickets tk, PcgState* st, double rtol, int32_t max_iter) {
+                                                  double* __restrict__ z, double* __restrict__ p_old,
+                                                  double* __restrict__ pb) {
   __shared__ double red[kWaves];
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   double rz = 0.0, rr = 0.0, bb = 0.0;
@@ -347,59 +461,58 @@ __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, 
     for (int k = 0; k < 3; ++k) {
       r[3 * i + k] = rv[k];
       z[3 * i + k] = zv[k];
-      p[3 * i + k] = zv[k];
+      p_old[3 * i + k] = 0.0;
       rz += rv[k] * zv[k];
       rr += rv[k] * rv[k];
     }
   }
-  const double v[3] = {wg_sum(rz, red), wg_sum(rr, red), wg_sum(bb, red)};
-  double tot[3];
-  if (!reduce_last<3>(v, tk, red, tot)) return;
-  const double trz = tot[0], trr = tot[1], tbb = tot[2];
+  const unsigned G = gridDim.x;
+  rz = wg_sum(rz, red);
+  rr = wg_sum(rr, red);
+  bb = wg_sum(bb, red);
   if (threadIdx.x == 0) {
-    st->rz = trz;
-    st->rr = trr;
-    st->bb = tbb;
-    st->tol2 = rtol * rtol * tbb;
-    st->iter = 0;
-    st->max_iter = max_iter;
-    st->ticket_a = 0;
-    st->ticket_b = 0;
-    st->ticket_c = 0;
-    int done = 0;
-    if (!(trr == trr) || !(trz == trz)) done = 3;
-    else if (tbb == 0.0 || trr <= st->tol2) done = 1;
-    else if (max_iter <= 0) done = 2;
-    st->done = done;
+    pb[blockIdx.x] = rz;
+    pb[G + blockIdx.x] = rr;
+    pb[2 * G + blockIdx.x] = bb;
   }
 }
 
 template <class T>
-__global__ __launch_bounds__(kWG) void k_pcg_a(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+__global__ __launch_bounds__(kWG) void k_pcg_a(int64_t j, const int32_t* __restrict__ col,
                                                const int32_t* __restrict__ ri, const T* __restrict__ vals,
-                                               int64_t nnzb, const double* __restrict__ p, double* __restrict__ q,
-                                               double* __restrict__ carry, Tickets tk, PcgState* st) {
+                                               int64_t nnzb, int64_t stride, const double* __restrict__ z,
+                                               const double* __restrict__ p_old, double* __restrict__ p_new,
+                                               double* __restrict__ q, double* __restrict__ carry,
+                                               const double* __restrict__ pb, unsigned gb, double* __restrict__ pa,
+                                               PcgState* st, double rtol) {
   __shared__ double red[kWaves];
+  __shared__ double bc[3];
   if (st->done) return;
-  const double v[1] = {spmv_tile<T>(rp, col, ri, vals, nnzb, p, q, carry, p, red)};
-  double tot[1];
-  if (!reduce_last<1>(v, tk, red, tot)) return;
-  const double pq = tot[0];
-  if (threadIdx.x == 0) {
-    st->pq = pq;
-    if (pq > 0.0 && pq == pq) st->alpha = st->rz / pq;
-    else st->done = 3;
-  }
+  int done;
+  double rz, beta;
+  iteration_scalars(j, pb, gb, st, rtol, red, bc, &done, &rz, &beta);
+  if (done) return;
+  const GatherP g{z, p_old, beta};
+  const double d = spmv_tile<T, GatherP, true, true>(ri, col, vals, nnzb, stride, g, q, carry, p_new, red);
+  if (threadIdx.x == 0) pa[blockIdx.x] = d;
 }
 
-__global__ __launch_bounds__(kWG) void k_pcg_b(const int32_t* __restrict__ rp, int32_t n,
+__global__ __launch_bounds__(kWG) void k_pcg_b(int64_t j, const int32_t* __restrict__ rp, int32_t n,
                                                const double* __restrict__ qy, const double* __restrict__ carry,
                                                const double* __restrict__ dinv, const double* __restrict__ p,
                                                double* __restrict__ x, double* __restrict__ r,
-                                               double* __restrict__ z, Tickets tk, PcgState* st) {
+                                               double* __restrict__ z, const double* __restrict__ pa, unsigned ga,
+                                               double* __restrict__ pb, PcgState* st) {
   __shared__ double red[kWaves];
+  __shared__ double bc[1];
   if (st->done) return;
-  const double alpha = st->alpha;
+  double pq[1];
+  all_sum<1>(pa, ga, red, bc, pq);
+  if (!(pq[0] > 0.0)) {   // p^T A p <= 0 or NaN: not SPD (every workgroup sees the same value)
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
+    return;
+  }
+  const double alpha = st->rz_hist[j & 1] / pq[0];
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   double rz = 0.0, rr = 0.0;
   if (i < n) {
@@ -419,27 +532,25 @@ __global__ __launch_bounds__(kWG) void k_pcg_b(const int32_t* __restrict__ rp, i
       rr += rv[k] * rv[k];
     }
   }
-  const double v[2] = {wg_sum(rz, red), wg_sum(rr, red)};
-  double tot[2];
-  if (!reduce_last<2>(v, tk, red, tot)) return;
-  const double trz = tot[0], trr = tot[1];
+  const unsigned G = gridDim.x;
+  rz = wg_sum(rz, red);
+  rr = wg_sum(rr, red);
   if (threadIdx.x == 0) {
-    st->beta = trz / st->rz;
-    st->rz = trz;
-    st->rr = trr;
-    st->iter += 1;
-    if (!(trr == trr) || !(trz == trz)) st->done = 3;
-    else if (trr <= st->tol2) st->done = 1;
-    else if (st->iter >= st->max_iter) st->done = 2;
+    pb[blockIdx.x] = rz;
+    pb[G + blockIdx.x] = rr;
+    pb[2 * G + blockIdx.x] = 0.0;
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_pcg_c(int64_t n3, const double* __restrict__ z, double* __restrict__ p,
-                                               const PcgState* st) {
+// The stop test of iteration j alone (one workgroup), run at the end of a chunk.
+__global__ __launch_bounds__(kWG) void k_pcg_check(int64_t j, const double* __restrict__ pb, unsigned gb,
+                                                   PcgState* st, double rtol) {
+  __shared__ double red[kWaves];
+  __shared__ double bc[3];
   if (st->done) return;
-  const double beta = st->beta;
-  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (i < n3) p[i] = z[i] + beta * p[i];
+  int done;
+  double rz, beta;
+  iteration_scalars(j, pb, gb, st, rtol, red, bc, &done, &rz, &beta);
 }
 
 int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters,
@@ -452,32 +563,30 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   double* dinv = c->ws.get<double>("pcg.dinv", 9 * (int64_t)n);
   double* r = c->ws.get<double>("pcg.r", n3);
   double* z = c->ws.get<double>("pcg.z", n3);
-  double* p = c->ws.get<double>("pcg.p", n3);
+  double* pp[2] = {c->ws.get<double>("pcg.p0", n3), c->ws.get<double>("pcg.p1", n3)};
   double* q = c->ws.get<double>("pcg.q", n3);
   const unsigned gr = blocks_for(n, kWG);
-  const unsigned gs = blocks_for(a.nnzb, kSpmvTile);
-  const unsigned gmax = gr > gs ? gr : gs;
-  const unsigned ngmax = (gmax + kTicketGroup - 1) / kTicketGroup;
-  // one ticket state serves the three kernels: they run one after another and
-  // every counter is back at zero when a kernel ends
-  const int64_t ncnt = (int64_t)(ngmax + 1) * kTicketStride;
-  uint32_t* cnt = c->ws.get<uint32_t>("pcg.tickets", ncnt);
-  Tickets tk{cnt, cnt + (int64_t)ngmax * kTicketStride, c->ws.get<double>("pcg.part", 3 * (int64_t)gmax),
-             c->ws.get<double>("pcg.gpart", 3 * (int64_t)ngmax)};
+  const unsigned gs = blocks_for(a.nnzb, kTile);
+  double* pb = c->ws.get<double>("pcg.pb", 3 * (int64_t)gr);
+  double* pa = c->ws.get<double>("pcg.pa", gs);
   double* carry = spmv_carry(c, a);
   PcgState* st = (PcgState*)c->d_pcg;
   PcgState* hs = (PcgState*)c->h_pcg;
+  *hs = PcgState{};
+  hs->max_iter = max_iter;
+  AGC_HIP(hipMemcpyAsync(st, hs, sizeof(PcgState), hipMemcpyHostToDevice, c->stream));
 
   err_reset(c);
-  AGC_HIP(hipMemsetAsync(st, 0, sizeof(PcgState), c->stream));
-  AGC_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * ncnt, c->stream));
   if (a.dtype == AGC_F64)
-    k_jacobi<double><<<gr, kWG, 0, c->stream>>>(a.dg(), (const double*)a.vals.p, a.nnzb, n, dinv, c->d_err);
+    k_jacobi<double><<<gr, kWG, 0, c->stream>>>(a.dg(), (const double*)a.vals.p, a.stride, n, dinv, c->d_err);
   else
-    k_jacobi<float><<<gr, kWG, 0, c->stream>>>(a.dg(), (const float*)a.vals.p, a.nnzb, n, dinv, c->d_err);
+    k_jacobi<float><<<gr, kWG, 0, c->stream>>>(a.dg(), (const float*)a.vals.p, a.stride, n, dinv, c->d_err);
   AGC_LAUNCH_CHECK();
   spmv(c, a, x, q);   // q = A x0
-  k_pcg_init<<<gr, kWG, 0, c->stream>>>(b, q, dinv, n, r, z, p, tk, st, rtol, max_iter);
+  // iteration j reads p_{j-1} from pp[(j+1)%2] and writes p_j to pp[j%2]
+  k_pcg_init<<<gr, kWG, 0, c->stream>>>(b, q, dinv, n, r, z, pp[1], pb);
+  AGC_LAUNCH_CHECK();
+  k_pcg_check<<<1, kWG, 0, c->stream>>>(0, pb, gr, st, rtol);
   AGC_LAUNCH_CHECK();
   if (err_fetch(c)) return AGC_ERR_NOT_SPD;
 
@@ -517,19 +626,22 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
     prev_it = hs->iter;
     prev_rr = hs->rr;
     chunk_start = launched;
-    launched += chunk;
     for (int it = 0; it < chunk; ++it) {
+      const int64_t j = launched + it;
+      const double* p_old = pp[(j + 1) & 1];
+      double* p_new = pp[j & 1];
       if (kt) AGC_HIP(hipEventRecord(c->kev[2 * it], c->stream));
       if (a.dtype == AGC_F64)
-        k_pcg_a<double><<<gs, kWG, 0, c->stream>>>(a.rp(), a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, p, q,
-                                                   carry, tk, st);
+        k_pcg_a<double><<<gs, kWG, 0, c->stream>>>(j, a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, a.stride, z,
+                                                   p_old, p_new, q, carry, pb, gr, pa, st, rtol);
       else
-        k_pcg_a<float><<<gs, kWG, 0, c->stream>>>(a.rp(), a.ci(), a.ri(), (const float*)a.vals.p, a.nnzb, p, q,
-                                                  carry, tk, st);
+        k_pcg_a<float><<<gs, kWG, 0, c->stream>>>(j, a.ci(), a.ri(), (const float*)a.vals.p, a.nnzb, a.stride, z,
+                                                  p_old, p_new, q, carry, pb, gr, pa, st, rtol);
       if (kt) AGC_HIP(hipEventRecord(c->kev[2 * it + 1], c->stream));
-      k_pcg_b<<<gr, kWG, 0, c->stream>>>(a.rp(), n, q, carry, dinv, p, x, r, z, tk, st);
-      k_pcg_c<<<blocks_for(n3, kWG), kWG, 0, c->stream>>>(n3, z, p, st);
+      k_pcg_b<<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, q, carry, dinv, p_new, x, r, z, pa, gs, pb, st);
     }
+    launched += chunk;
+    k_pcg_check<<<1, kWG, 0, c->stream>>>(launched, pb, gr, st, rtol);
     AGC_LAUNCH_CHECK();
   }
   *iters = hs->iter;
