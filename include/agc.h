@@ -97,7 +97,8 @@ agc_status agc_mesh_info(const agc_mesh* mesh, int32_t* n_verts, int64_t* n_elem
  * its smallest vertex id, which is the order the supplement's elected-lane
  * popcount and group prefix sum produce (supplement Alg. 2, Sec. 1.3).
  *   edges    : [n_edges][2] int32 vertex ids, unordered; duplicates and
- *              self-loops allowed (a self-loop joins nothing).
+ *              self-loops allowed (a self-loop joins nothing); 8-byte
+ *              aligned (AGC_ERR_INVALID_ARG otherwise).
  *   tags     : [n_edges] uint8, 1 = collapsible, 0 = protected.
  *   map      : [n_verts] int32 out.
  *   n_coarse : [host] out, number of super-nodes.  Synchronises.
@@ -185,20 +186,20 @@ typedef struct {
   const uint8_t* tags;     /* [n_edges] uint8                                  */
   const double* elem_H;    /* [n_elems][144] float64 element blocks, 16-byte
                               aligned (AGC_ERR_INVALID_ARG otherwise)         */
-  const float* elem_H32;   /* optional float32 copy of elem_H for the mixed
-                              inner assembly (NULL: convert elem_H on load)   */
   const double* g;         /* [n_verts][3] float64 gradient                    */
 } agc_problem;
 
 typedef struct {
-  int32_t precision;   /* AGC_PREC_FP64, or AGC_PREC_MIXED: float32 assembly,
-                          storage and SpMV values; float64 vectors, inner
-                          products, residuals and iterative refinement       */
+  int32_t precision;   /* AGC_PREC_FP64, or AGC_PREC_MIXED: float32 storage
+                          and SpMV values in the inner PCG; float64
+                          assembly sums, vectors, inner products, residuals
+                          and iterative refinement                           */
   int32_t coarsen;     /* 1: aggregate by tags; 0: fine solve (map = identity) */
   double rtol;         /* target ||b_c - A_c x_c||_2 / ||b_c||_2 in float64    */
   int32_t max_iter;    /* PCG iteration cap (over all refinement steps)        */
   double inner_rtol;   /* mixed: relative tolerance of each inner PCG solve    */
-  int32_t max_refine;  /* mixed: cap on refinement steps                       */
+  int32_t max_refine;  /* mixed: cap on inner solves (the first one and its
+                          refinement steps)                                   */
   int32_t timing;      /* 1: fill the ms_* phase times of agc_solve_info;
                           2: also time every PCG SpMV launch with HIP events
                           (spmv_launches, ms_spmv)                            */
@@ -208,7 +209,8 @@ typedef struct {
   int32_t n_coarse;    /* super-nodes (n_verts when coarsen = 0)               */
   int64_t nnzb;        /* stored blocks of the solved matrix                   */
   int32_t pcg_iters;   /* PCG iterations over all refinement steps             */
-  int32_t refine_iters;/* refinement steps (0 for AGC_PREC_FP64)               */
+  int32_t refine_iters;/* mixed: inner solves after the first, each on the
+                          float64 residual b_c - A_c x_c (0 for FP64)        */
   double rel_res;      /* final float64 relative residual of the coarse system */
   float ms_aggregate, ms_assemble, ms_pcg, ms_prolong;  /* when timing >= 1   */
   int32_t spmv_launches;  /* when timing = 2: PCG SpMV launches that did work  */

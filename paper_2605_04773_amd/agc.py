@@ -55,7 +55,7 @@ class BadInput(AgcError):
 
 class agc_problem(ctypes.Structure):
     _fields_ = [("mesh", c_void_p), ("n_edges", c_int64), ("edges", c_void_p), ("tags", c_void_p),
-                ("elem_H", c_void_p), ("elem_H32", c_void_p), ("g", c_void_p)]
+                ("elem_H", c_void_p), ("g", c_void_p)]
 
 
 class agc_solve_opts(ctypes.Structure):
@@ -328,17 +328,15 @@ def make_opts(precision=AGC_PREC_FP64, coarsen=1, rtol=1e-10, max_iter=20000, in
                           int(max_refine), int(timing))
 
 
-def make_problem(mesh: Mesh, edges, tags, elem_H, g, elem_H32=None) -> agc_problem:
+def make_problem(mesh: Mesh, edges, tags, elem_H, g) -> agc_problem:
     ctx = mesh.ctx
     m = 0 if edges is None else edges.shape[0]
     if edges is not None:
         _dev(edges, torch.int32, (m, 2), "edges", ctx.device)
         _dev(tags, torch.uint8, (m,), "tags", ctx.device)
     _dev(elem_H, torch.float64, (mesh.n_elems, 144), "elem_H", ctx.device)
-    if elem_H32 is not None:
-        _dev(elem_H32, torch.float32, (mesh.n_elems, 144), "elem_H32", ctx.device)
     _dev(g, torch.float64, (mesh.n_verts, 3), "g", ctx.device)
-    return agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(elem_H32), _ptr(g))
+    return agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g))
 
 
 def agc_solve(ctx: Context, prob: agc_problem, opts: agc_solve_opts, x: torch.Tensor, map_out=None):

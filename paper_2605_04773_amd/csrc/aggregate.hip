@@ -44,10 +44,15 @@ __global__ void k_cc_init(int32_t* __restrict__ parent, int32_t n) {
     parent[v] = (int32_t)v;
 }
 
-__global__ void k_cc_hook(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
-                          int32_t* parent, int32_t n, unsigned* err) {
+// Pre-linking: every vertex points at its smallest neighbour over a
+// collapsible edge (if smaller than itself).  The atomics of one vertex
+// number its lower neighbours only, so they barely contend, and afterwards
+// most edges of a component already lead to one root.  Also validates.
+__global__ void k_cc_link_min(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
+                              int32_t* parent, int32_t n, unsigned* err) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t u = edges[2 * e], v = edges[2 * e + 1];
+    const int2 uv = reinterpret_cast<const int2*>(edges)[e];
+    const int32_t u = uv.x, v = uv.y;
     const uint8_t t = tags[e];
     if (u < 0 || u >= n || v < 0 || v >= n) {
       atomicOr(err, kErrRange);
@@ -58,6 +63,30 @@ __global__ void k_cc_hook(const int32_t* __restrict__ edges, const uint8_t* __re
       continue;
     }
     if (t == 0 || u == v) continue;
+    const int32_t lo = u < v ? u : v, hi = u < v ? v : u;
+    atomicMin(parent + hi, lo);
+  }
+}
+
+// One round of pointer jumping: parent[v] = parent[parent[v]].  Values only
+// move to ancestors, so reading entries another thread has already updated
+// is harmless.
+__global__ void k_cc_jump(int32_t* parent, int32_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = parent[v];
+    const int32_t pp = parent[p];
+    if (pp != p) parent[v] = pp;
+  }
+}
+
+// Lock-free union of the remaining edges whose ends sit in different trees
+// (input already validated by k_cc_link_min).
+__global__ void k_cc_hook(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
+                          int32_t* parent, int32_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int2 uv = reinterpret_cast<const int2*>(edges)[e];
+    const int32_t u = uv.x, v = uv.y;
+    if (tags[e] != 1 || u == v || u < 0 || u >= n || v < 0 || v >= n) continue;
     int32_t ru = find_root(parent, u), rv = find_root(parent, v);
     while (ru != rv) {
       const int32_t lo = ru < rv ? ru : rv, hi = ru < rv ? rv : ru;
@@ -86,6 +115,10 @@ __global__ void k_cc_label(const int32_t* __restrict__ parent, const uint32_t* _
   }
 }
 
+// Jumping rounds before the hooking pass; each halves every path, and the
+// hooking pass's own path shortening handles whatever remains.
+constexpr int kJumpRounds = 4;
+
 static unsigned gs_blocks(int64_t n) {
   int64_t b = (n + kWG - 1) / kWG;
   if (b > 65536) b = 65536;
@@ -100,7 +133,11 @@ int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, co
   k_cc_init<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
   AGC_LAUNCH_CHECK();
   if (m > 0) {
-    k_cc_hook<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n, c->d_err);
+    k_cc_link_min<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n, c->d_err);
+    AGC_LAUNCH_CHECK();
+    for (int r = 0; r < kJumpRounds; ++r) k_cc_jump<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
+    AGC_LAUNCH_CHECK();
+    k_cc_hook<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n);
     AGC_LAUNCH_CHECK();
   }
   k_cc_compress<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n, flag);
@@ -144,12 +181,11 @@ void group_members(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, u
 struct RestrictOp {
   const uint32_t* members;
   const double* v;
-  const double* sub;
   double* out;
   __device__ void load(int64_t k, double x[3]) const {
     const int64_t i = members[k];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) x[r] = sub ? v[3 * i + r] - sub[3 * i + r] : v[3 * i + r];
+    for (int r = 0; r < 3; ++r) x[r] = v[3 * i + r];
   }
   __device__ void store(int64_t s, const double x[3]) const {
 #pragma unroll
@@ -164,9 +200,9 @@ struct RestrictOp {
 // members/mkeys from group_members; every coarse id has at least one member,
 // so segment s is coarse node s.
 void restrict_sorted(agc_context* c, int32_t n, int32_t n_c, const uint32_t* members, const uint32_t* mkeys,
-                     const double* v, const double* sub, double* v_c) {
+                     const double* v, double* v_c) {
   (void)n_c;
-  RestrictOp op{members, v, sub, v_c};
+  RestrictOp op{members, v, v_c};
   seg_reduce<3, double, uint32_t, RestrictOp>(c, mkeys, n, op, (uint32_t*)nullptr, false, "rst.seg");
 }
 

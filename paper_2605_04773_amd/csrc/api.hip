@@ -98,6 +98,7 @@ void validate_problem(const agc_problem* p) {
   AGC_REQUIRE(p->elem_H && p->g, "elem_H and g are required");
   AGC_REQUIRE(((uintptr_t)p->elem_H & 15) == 0, "elem_H must be 16-byte aligned");
   AGC_REQUIRE(p->n_edges >= 0, "n_edges < 0");
+  AGC_REQUIRE(((uintptr_t)p->edges & 7) == 0, "edges must be 8-byte aligned");
 }
 
 // Solves A_c x_c = b_c for the matrix assembled from the problem.
@@ -109,16 +110,10 @@ struct Restrictor {
   const int32_t* map;        // nullptr: identity
   const uint32_t* members;
   const uint32_t* mkeys;
-  // out = P^T (v - sub)
-  void apply(const double* v, const double* sub, double* out) const {
-    if (map) {
-      agc::restrict_sorted(c, n, n_c, members, mkeys, v, sub, out);
-    } else if (sub) {
-      AGC_HIP(hipMemcpyAsync(out, v, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
-      agc::axpy_vec(c, out, sub, -1.0, 3 * (int64_t)n);
-    } else {
-      AGC_HIP(hipMemcpyAsync(out, v, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
-    }
+  // out = P^T v
+  void apply(const double* v, double* out) const {
+    if (map) agc::restrict_sorted(c, n, n_c, members, mkeys, v, out);
+    else AGC_HIP(hipMemcpyAsync(out, v, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
   }
 };
 
@@ -136,66 +131,58 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   const int64_t n3c = 3 * (int64_t)n_c;
   SolveResult res;
   double* b_c = c->ws.get<double>("solve.b", n3c);
-  R.apply(rhs_fine, nullptr, b_c);
-  AGC_HIP(hipMemsetAsync(x_c, 0, sizeof(double) * n3c, c->stream));
-  if (o->precision == AGC_PREC_FP64) {
-    agc::Matrix& A = c->solve_a64;
-    if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, n_c, AGC_F64, A);
-    else agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, A);
-    res.nnzb = A.nnzb;
-    if (tm) tm->mark();
+  R.apply(rhs_fine, b_c);
+  // Both precisions assemble P^T H P once in float64 (the reduction sums in
+  // float64); the mixed path also keeps the float32 rounding of the values
+  // for its inner PCG.  The float64 matrix gives the float64 residuals.
+  const bool mixed = o->precision == AGC_PREC_MIXED;
+  agc::Matrix& A64 = c->solve_a64;
+  agc::Matrix* A32 = mixed ? &c->solve_a : nullptr;
+  if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, n_c, AGC_F64, A64, A32);
+  else agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, A64, A32);
+  res.nnzb = A64.nnzb;
+  if (tm) tm->mark();
+  double* y = c->ws.get<double>("solve.y", n3c);
+  double* r_c = c->ws.get<double>("solve.rc", n3c);
+  double bn = 0.0, rn = 0.0;
+  if (!mixed) {
     int32_t it = 0;
     double rel = 0.0;
-    check_status(agc::pcg(c, A, b_c, x_c, o->rtol, o->max_iter, &it, &rel), "coarse PCG");
+    check_status(agc::pcg(c, A64, b_c, x_c, o->rtol, o->max_iter, &it, &rel, true), "coarse PCG");
     res.iters = it;
     // float64 residual of the returned iterate
-    double* r = c->ws.get<double>("solve.r", n3c);
-    agc::spmv(c, A, x_c, r);
-    agc::axpy_vec(c, r, b_c, -1.0, n3c);
-    const double bn = agc::norm2(c, b_c, n3c, "solve.nb");
-    res.rel = bn > 0 ? agc::norm2(c, r, n3c, "solve.nr") / bn : 0.0;
+    agc::spmv(c, A64, x_c, y);
+    agc::residual_norms(c, b_c, y, r_c, n3c, &bn, &rn);
+    res.rel = bn > 0 ? rn / bn : 0.0;
     return res;
   }
-  // mixed: float32 assembly, storage and SpMV values; float64 vectors, inner
-  // products, residuals (matrix-free from the float64 element blocks) and
-  // iterative refinement x_c += A32^{-1} (b_c - A64 x_c)
-  agc::Matrix& A = c->solve_a;
-  const void* eh = p->elem_H32 ? (const void*)p->elem_H32 : (const void*)p->elem_H;
-  const int32_t hd = p->elem_H32 ? AGC_F32 : AGC_F64;
-  if (R.map) agc::assemble_coarse(c, mesh, eh, hd, R.map, n_c, AGC_F32, A);
-  else agc::assemble_fine(c, mesh, eh, hd, AGC_F32, A);
-  res.nnzb = A.nnzb;
-  if (tm) tm->mark();
-  const double bn = agc::norm2(c, b_c, n3c, "solve.nb");
-  double* r_c = c->ws.get<double>("solve.rc", n3c);
+  // mixed: iterative refinement x_c += A32^{-1} (b_c - A64 x_c), the inner
+  // solves on the float32 values with float64 vectors and inner products
   double* e_c = c->ws.get<double>("solve.ec", n3c);
-  double* rf = c->ws.get<double>("solve.rf", 3 * (int64_t)mesh.n_verts);
-  if (bn == 0.0) return res;
-  AGC_HIP(hipMemcpyAsync(r_c, b_c, sizeof(double) * n3c, hipMemcpyDeviceToDevice, c->stream));
   double rel = 1.0;
   int32_t used = 0;
   for (int k = 0;; ++k) {
     if (rel <= o->rtol) break;
     if (k >= o->max_refine || used >= o->max_iter)
       throw Error(AGC_ERR_NOT_CONVERGED, "mixed refinement did not reach rtol");
-    AGC_HIP(hipMemsetAsync(e_c, 0, sizeof(double) * n3c, c->stream));
     int32_t it = 0;
     double irel = 0.0;
     // the inner tolerance is relative to ||r_c||; never ask for more than rtol needs
     const double want = o->rtol / rel;
     const double itol = want > o->inner_rtol ? want : o->inner_rtol;
-    const int st = agc::pcg(c, A, r_c, e_c, itol, o->max_iter - used, &it, &irel);
+    const int st = agc::pcg(c, *A32, k == 0 ? b_c : r_c, k == 0 ? x_c : e_c, itol, o->max_iter - used, &it,
+                            &irel, true);
     used += it;
     if (st != AGC_OK && st != AGC_ERR_NOT_CONVERGED) check_status(st, "inner PCG");
-    agc::axpy_vec(c, x_c, e_c, 1.0, n3c);
-    res.refine = k + 1;
-    // r_c = P^T (g - H P x_c) in float64
-    agc::elem_residual(c, mesh, p->elem_H, R.map, x_c, rhs_fine, rf);
-    R.apply(rf, nullptr, r_c);
-    rel = agc::norm2(c, r_c, n3c, "solve.nr") / bn;
+    if (k > 0) agc::axpy_vec(c, x_c, e_c, 1.0, n3c);
+    res.refine = k;
+    agc::spmv(c, A64, x_c, y);
+    agc::residual_norms(c, b_c, y, r_c, n3c, &bn, &rn);
+    if (bn == 0.0) break;
+    rel = rn / bn;
   }
   res.iters = used;
-  res.rel = rel;
+  res.rel = bn > 0 ? rel : 0.0;
   return res;
 }
 
@@ -305,6 +292,7 @@ agc_status agc_aggregate(agc_context* c, int32_t n_verts, int64_t n_edges, const
   AGC_REQUIRE(n_coarse, "n_coarse is null");
   AGC_REQUIRE(n_verts == 0 || map, "map is null");
   AGC_REQUIRE(n_edges == 0 || (edges && tags), "edges/tags null");
+  AGC_REQUIRE(((uintptr_t)edges & 7) == 0, "edges must be 8-byte aligned");
   *n_coarse = agc::aggregate(c, n_verts, n_edges, edges, tags, map);
   API_END(c)
 }
@@ -316,7 +304,7 @@ static void restrict_api(agc_context* c, int32_t n, const int32_t* map, int32_t 
   uint32_t* mkeys = c->ws.get<uint32_t>("api.mkeys", n);
   agc::group_members(c, n, map, n_c, members, mkeys);
   agc::err_throw(agc::err_fetch(c));
-  agc::restrict_sorted(c, n, n_c, members, mkeys, v, nullptr, v_c);
+  agc::restrict_sorted(c, n, n_c, members, mkeys, v, v_c);
 }
 
 agc_status agc_assemble_coarse(agc_context* c, const agc_mesh* mesh, const void* elem_H, int32_t h_dtype,

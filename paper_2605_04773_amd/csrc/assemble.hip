@@ -232,24 +232,6 @@ static int64_t build_full(agc_context* c, int32_t n, int64_t nu, const int32_t* 
 
 // ------------------------------------------------------------ mesh build
 
-__global__ void k_vert_incidence(const int32_t* __restrict__ ev, int64_t ne, uint32_t* __restrict__ keys,
-                                 uint32_t* __restrict__ vals) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 4 * ne; k += (int64_t)gridDim.x * blockDim.x) {
-    keys[k] = (uint32_t)ev[k];
-    vals[k] = (uint32_t)k;  // e*4 + a
-  }
-}
-
-__global__ void k_vert_ptr(const uint32_t* __restrict__ sorted_v, int64_t m, int32_t n, uint32_t* __restrict__ ptr) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t v = sorted_v[k];
-    const uint32_t pv = (k == 0) ? 0u : sorted_v[k - 1] + 1u;
-    for (uint32_t u = (k == 0 ? 0u : pv); u <= v; ++u) ptr[u] = (uint32_t)k;   // vertices with no element get empty ranges
-    if (k == m - 1)
-      for (int64_t u = (int64_t)v + 1; u <= n; ++u) ptr[u] = (uint32_t)m;
-  }
-}
-
 void mesh_build(agc_context* c, Mesh& m, int32_t n, int64_t ne, const int32_t* ev) {
   m.n_verts = n;
   m.n_elems = ne;
@@ -305,74 +287,92 @@ void mesh_build(agc_context* c, Mesh& m, int32_t n, int64_t ne, const int32_t* e
   err_throw(err_fetch(c));
   m.ff_nnzb = nnz;
 
-  // vertex -> (element, local vertex)
-  const int64_t ni = 4 * ne;
-  uint32_t* ik = c->ws.get<uint32_t>("mesh.ik", ni);
-  uint32_t* ik2 = c->ws.get<uint32_t>("mesh.ik2", ni);
-  uint32_t* iv = c->ws.get<uint32_t>("mesh.iv", ni);
-  uint32_t* iv2 = c->ws.get<uint32_t>("mesh.iv2", ni);
-  k_vert_incidence<<<grid_stride_blocks(ni), kWG, 0, c->stream>>>(evd, ne, ik, iv);
-  AGC_LAUNCH_CHECK();
-  const bool ialt = radix_sort_u32(c, ik, iv, ik2, iv2, ni, bits_for((uint64_t)(n - 1)), "mesh.isort");
-  uint32_t* vp = (uint32_t*)m.va_ptr.ensure(sizeof(uint32_t) * (n + 1));
-  uint32_t* va = (uint32_t*)m.va.ensure(sizeof(uint32_t) * ni);
-  k_vert_ptr<<<grid_stride_blocks(ni), kWG, 0, c->stream>>>(ialt ? ik2 : ik, ni, n, vp);
-  AGC_LAUNCH_CHECK();
-  AGC_HIP(hipMemcpyAsync(va, ialt ? iv2 : iv, sizeof(uint32_t) * ni, hipMemcpyDeviceToDevice, c->stream));
   AGC_HIP(hipStreamSynchronize(c->stream));
 }
 
 // ------------------------------------------------------- per-step assembly
 
-// F[s][f] = sum over the plan of f of element sub-block (a, b), in plan order.
+// F[3r+s][f] = sum over the plan of f of entry (r, s) of element sub-block
+// (a, b), in plan order.  Three threads per fine block, one per row r: each
+// reads three contiguous values per plan entry, and the loop is unrolled so
+// that the loads of several entries are in flight together (the sums keep
+// plan order).
+constexpr int kGatherUnroll = 4;
 template <class In, class Acc>
 __global__ __launch_bounds__(kWG) void k_fine_gather(const In* __restrict__ eh, const uint32_t* __restrict__ pptr,
                                                      const uint32_t* __restrict__ plan, int64_t nf,
                                                      Acc* __restrict__ F) {
-  const int64_t f = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (f >= nf) return;
-  Acc acc[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) acc[i] = (Acc)0;
+  const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (t >= 3 * nf) return;
+  const int64_t f = t / 3;
+  const int r = (int)(t - 3 * f);
+  Acc acc[3] = {(Acc)0, (Acc)0, (Acc)0};
   const uint32_t k0 = pptr[f], k1 = pptr[f + 1];
-  for (uint32_t k = k0; k < k1; ++k) {
+  uint32_t k = k0;
+  for (; k + kGatherUnroll <= k1; k += kGatherUnroll) {
+    In v[kGatherUnroll][3];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const uint32_t code = plan[k + u];
+      const In* p = eh + (int64_t)(code >> 4) * 144 + (3 * ((code >> 2) & 3) + r) * 12 + 3 * (code & 3);
+#pragma unroll
+      for (int s = 0; s < 3; ++s) v[u][s] = p[s];
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) acc[s] += (Acc)v[u][s];
+  }
+  for (; k < k1; ++k) {
     const uint32_t code = plan[k];
-    const int64_t e = code >> 4;
-    const int a = (code >> 2) & 3, b = code & 3;
-    const In* p = eh + e * 144 + (3 * a) * 12 + 3 * b;
+    const In* p = eh + (int64_t)(code >> 4) * 144 + (3 * ((code >> 2) & 3) + r) * 12 + 3 * (code & 3);
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int s = 0; s < 3; ++s) acc[3 * r + s] += (Acc)p[r * 12 + s];
+    for (int s = 0; s < 3; ++s) acc[s] += (Acc)p[s];
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) F[(int64_t)i * nf + f] = acc[i];
+  for (int s = 0; s < 3; ++s) F[(int64_t)(3 * r + s) * nf + f] = acc[s];
 }
 
 // Full matrix values (planes of stride vs) from upper blocks U (planes of
-// stride us) and src.
+// stride us) and src; vals32 != nullptr also receives the values rounded to
+// float32 (same pattern and stride).
 template <class Acc>
 __global__ __launch_bounds__(kWG) void k_fill_vals(const uint32_t* __restrict__ src, int64_t nnz,
                                                    const Acc* __restrict__ U, int64_t us,
-                                                   Acc* __restrict__ vals, int64_t vs) {
+                                                   Acc* __restrict__ vals, int64_t vs, float* __restrict__ vals32) {
   const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (p >= nnz) return;
   const uint32_t s = src[p];
   const int64_t u = s >> 1;
+  Acc v[9];
   if (s & 1u) {
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) vals[(int64_t)(3 * r + q) * vs + p] = U[(int64_t)(3 * q + r) * us + u];
+      for (int q = 0; q < 3; ++q) v[3 * r + q] = U[(int64_t)(3 * q + r) * us + u];
   } else {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) vals[(int64_t)i * vs + p] = U[(int64_t)i * us + u];
+    for (int i = 0; i < 9; ++i) v[i] = U[(int64_t)i * us + u];
   }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) vals[(int64_t)i * vs + p] = v[i];
+  if (vals32) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) vals32[(int64_t)i * vs + p] = (float)v[i];
+  }
+}
+
+// A float32 companion of a float64 matrix: same (borrowed) pattern and stride.
+static float* companion32(const Matrix& a, Matrix* out32) {
+  if (!out32) return nullptr;
+  out32->reserve_values(a.n, a.nnzb, AGC_F32);
+  out32->borrow_pattern(a.rp(), a.ci(), a.ri(), a.dg());
+  return (float*)out32->vals.p;
 }
 
 template <class In, class Acc>
 static void gather_fine(agc_context* c, const Mesh& m, const void* eh, Acc* F) {
-  k_fine_gather<In, Acc><<<blocks_for(m.nf, kWG), kWG, 0, c->stream>>>(
+  k_fine_gather<In, Acc><<<blocks_for(3 * m.nf, kWG), kWG, 0, c->stream>>>(
       (const In*)eh, (const uint32_t*)m.plan_ptr.p, (const uint32_t*)m.plan.p, m.nf, F);
   AGC_LAUNCH_CHECK();
 }
@@ -387,7 +387,8 @@ static Acc* fine_upper(agc_context* c, const Mesh& m, const void* eh, int32_t h_
 
 // The fine matrix borrows the mesh's static pattern (no copy per assembly).
 void assemble_fine(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, int32_t out_dtype,
-                   Matrix& out) {
+                   Matrix& out, Matrix* out32) {
+  AGC_REQUIRE(!out32 || out_dtype == AGC_F64, "a float32 companion needs a float64 matrix");
   const int32_t n = m.n_verts;
   const int64_t nnz = m.ff_nnzb;
   out.reserve_values(n, nnz, out_dtype);
@@ -395,12 +396,13 @@ void assemble_fine(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtyp
                      (const int32_t*)m.ff_diag.p);
   if (out_dtype == AGC_F64) {
     double* F = fine_upper<double>(c, m, eh, h_dtype);
+    float* v32 = companion32(out, out32);
     k_fill_vals<double><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>((const uint32_t*)m.ff_src.p, nnz, F, m.nf,
-                                                                    (double*)out.vals.p, out.stride);
+                                                                    (double*)out.vals.p, out.stride, v32);
   } else {
     float* F = fine_upper<float>(c, m, eh, h_dtype);
     k_fill_vals<float><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>((const uint32_t*)m.ff_src.p, nnz, F, m.nf,
-                                                                   (float*)out.vals.p, out.stride);
+                                                                   (float*)out.vals.p, out.stride, nullptr);
   }
   AGC_LAUNCH_CHECK();
 }
@@ -470,7 +472,7 @@ struct CoarseOp {
 
 template <class Acc>
 static void coarse_impl(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, const int32_t* map,
-                        int32_t n_c, Matrix& out) {
+                        int32_t n_c, Matrix& out, Matrix* out32) {
   const int64_t nf = m.nf;
   Acc* F = fine_upper<Acc>(c, m, eh, h_dtype);
   uint64_t* k1 = c->ws.get<uint64_t>("asm.k1", nf);
@@ -501,72 +503,17 @@ static void coarse_impl(agc_context* c, const Mesh& m, const void* eh, int32_t h
   AGC_HIP(hipMemcpyAsync(&nnz, out.rp() + n_c, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   err_throw(err_fetch(c));
   out.set_nnzb(nnz);
-  k_fill_vals<Acc><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>(src, nnz, U, nf, (Acc*)out.vals.p, out.stride);
+  float* v32 = companion32(out, out32);
+  k_fill_vals<Acc><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>(src, nnz, U, nf, (Acc*)out.vals.p, out.stride, v32);
   AGC_LAUNCH_CHECK();
 }
 
 void assemble_coarse(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, const int32_t* map,
-                     int32_t n_c, int32_t out_dtype, Matrix& out) {
+                     int32_t n_c, int32_t out_dtype, Matrix& out, Matrix* out32) {
   AGC_REQUIRE(n_c >= 1 && n_c <= m.n_verts, "n_coarse out of range");
-  if (out_dtype == AGC_F64) coarse_impl<double>(c, m, eh, h_dtype, map, n_c, out);
-  else coarse_impl<float>(c, m, eh, h_dtype, map, n_c, out);
-}
-
-// --------------------------------------------- matrix-free float64 residual
-
-// ye[12 e + i] = row i of H_e times (P x_c) restricted to element e.  One
-// thread per (element, row): consecutive threads stream consecutive 96-byte
-// rows of the element blocks, so every byte of elem_H is read once.
-__global__ __launch_bounds__(kWG) void k_elem_rows(const double* __restrict__ eh, const int32_t* __restrict__ ev,
-                                                   int64_t ne, const int32_t* __restrict__ map,
-                                                   const double* __restrict__ xc, double* __restrict__ ye) {
-  const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (t >= 12 * ne) return;
-  const int64_t e = t / 12;
-  const double2* h = reinterpret_cast<const double2*>(eh + 12 * t);   // row t of the stacked blocks
-  double acc = 0.0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int u = ev[4 * e + b];
-    const int64_t cu = 3 * (int64_t)(map ? map[u] : u);
-    const double2 h01 = h[(3 * b) / 2 + 0];
-    const double2 h23 = h[(3 * b) / 2 + 1];
-    // row entries 3b, 3b+1, 3b+2 of the 12 (pairs are 16-byte aligned)
-    double c0, c1, c2;
-    if ((b & 1) == 0) { c0 = h01.x; c1 = h01.y; c2 = h23.x; }
-    else { c0 = h01.y; c1 = h23.x; c2 = h23.y; }
-    acc += c0 * xc[cu] + c1 * xc[cu + 1] + c2 * xc[cu + 2];
-  }
-  ye[t] = acc;
-}
-
-// rf[v] = g[v] - sum over incident (e, a) of ye[12 e + 3 a + r], fixed order.
-__global__ __launch_bounds__(kWG) void k_vert_residual(const double* __restrict__ ye, const uint32_t* __restrict__ vptr,
-                                                       const uint32_t* __restrict__ va, const double* __restrict__ g,
-                                                       int32_t n, double* __restrict__ rf) {
-  const int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (v >= n) return;
-  double acc[3] = {0.0, 0.0, 0.0};
-  const uint32_t k0 = vptr[v], k1 = vptr[v + 1];
-  for (uint32_t k = k0; k < k1; ++k) {
-    const uint32_t code = va[k];            // e*4 + a
-    const double* y = ye + 3 * (int64_t)code;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) acc[r] += y[r];
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) rf[3 * v + r] = g[3 * v + r] - acc[r];
-}
-
-void elem_residual(agc_context* c, const Mesh& m, const double* eh, const int32_t* map, const double* xc,
-                   const double* g, double* rf) {
-  double* ye = c->ws.get<double>("res.ye", 12 * m.n_elems);
-  k_elem_rows<<<blocks_for(12 * m.n_elems, kWG), kWG, 0, c->stream>>>(eh, (const int32_t*)m.elem_verts.p,
-                                                                      m.n_elems, map, xc, ye);
-  AGC_LAUNCH_CHECK();
-  k_vert_residual<<<blocks_for(m.n_verts, kWG), kWG, 0, c->stream>>>(ye, (const uint32_t*)m.va_ptr.p,
-                                                                     (const uint32_t*)m.va.p, g, m.n_verts, rf);
-  AGC_LAUNCH_CHECK();
+  AGC_REQUIRE(!out32 || out_dtype == AGC_F64, "a float32 companion needs a float64 matrix");
+  if (out_dtype == AGC_F64) coarse_impl<double>(c, m, eh, h_dtype, map, n_c, out, out32);
+  else coarse_impl<float>(c, m, eh, h_dtype, map, n_c, out, nullptr);
 }
 
 // -------------------------------------------------------- adjoint outer product

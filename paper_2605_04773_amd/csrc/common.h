@@ -94,6 +94,25 @@ enum : unsigned { kErrRange = 1u, kErrTag = 2u, kErrElem = 4u, kErrMap = 8u, kEr
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
+// Workgroups are dispatched round-robin over the eight XCDs (each with its
+// own L2).  This renumbering gives XCD x the contiguous range of blocks
+// [x*q + min(x, rem), ...) so that neighbouring tiles, and the vector
+// entries they gather, share one L2.  A bijection for any grid size.
+constexpr unsigned kXcds = 8;
+#ifndef AGC_XCD_MAP
+#define AGC_XCD_MAP 1
+#endif
+__device__ __forceinline__ int64_t xcd_block() {
+#if AGC_XCD_MAP
+  const unsigned b = blockIdx.x, G = gridDim.x;
+  const unsigned x = b % kXcds, i = b / kXcds;
+  const unsigned q = G / kXcds, rem = G % kXcds;
+  return (int64_t)x * q + (x < rem ? x : rem) + i;
+#else
+  return blockIdx.x;
+#endif
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   return (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
 }
@@ -130,21 +149,84 @@ __device__ __forceinline__ uint32_t wg_exclusive_scan(uint32_t v, uint32_t* lds,
   return off + x - v;
 }
 
-// Fixed-order workgroup sum of one double per thread (tree over lanes, then waves).
-__device__ __forceinline__ double wg_sum(double v, double* lds) {
-  const unsigned lane = lane_id();
+// ------------------------------------------------------ wave64 DPP moves
+// GFX9 data-parallel-primitive lane moves (VALU, no LDS traffic).  A lane
+// whose source lies outside the pattern, or whose 16-lane row is masked off,
+// keeps `old`.  Every lane of the wave must be active.
+enum : int {
+  kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118,
+  kDppRowBcast15 = 0x142,   // lane 15 of each row -> the next row
+  kDppRowBcast31 = 0x143,   // lane 31 -> rows 2 and 3
+  kDppWaveShr1 = 0x138      // lane i-1 -> lane i
+};
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int32_t dpp_move(int32_t old, int32_t x) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double old, double x) {
+  const int32_t lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(x), CTRL, ROWS, 0xf, false);
+  const int32_t hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(x), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One Hillis-Steele step of a segmented inclusive scan: add the value of the
+// source lane when it carries the same key.  Keys never equal INT32_MIN.
+template <int CTRL, int ROWS, int N>
+__device__ __forceinline__ void seg_scan_step(int32_t key, double (&v)[N]) {
+  const int32_t ku = dpp_move<CTRL, ROWS>((int32_t)INT32_MIN, key);
+  double vu[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) vu[i] = dpp_move<CTRL, ROWS>(0.0, v[i]);
+  if (ku == key) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += vu[i];
+  }
+}
+
+// Segmented inclusive scan over the wave of N doubles per lane, segments
+// being runs of equal, non-decreasing keys: shifts 1, 2, 4, 8 inside each
+// row of 16 lanes, then row 0 -> 1 and 2 -> 3, then lane 31 -> rows 2, 3.
+// The order of additions is fixed.
+template <int N>
+__device__ __forceinline__ void wave_seg_scan(int32_t key, double (&v)[N]) {
+  seg_scan_step<kDppRowShr1, 0xf>(key, v);
+  seg_scan_step<kDppRowShr2, 0xf>(key, v);
+  seg_scan_step<kDppRowShr4, 0xf>(key, v);
+  seg_scan_step<kDppRowShr8, 0xf>(key, v);
+  seg_scan_step<kDppRowBcast15, 0xa>(key, v);
+  seg_scan_step<kDppRowBcast31, 0xc>(key, v);
+}
+
+// Fixed-order sums of K doubles per thread over the workgroup with one
+// barrier; every thread receives the totals.  lds holds K * kWaves doubles
+// and must not be reused before another barrier.
+template <int K>
+__device__ __forceinline__ void wg_sum_all(double (&v)[K], double* lds) {
+  wave_seg_scan<K>(0, v);
   const unsigned wave = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) {
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_down(v, d);
-  if (lane == 0) lds[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) t += lds[w];
+    for (int k = 0; k < K; ++k) lds[k * kWaves + wave] = v[k];
   }
   __syncthreads();
-  return t;  // valid in thread 0
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += lds[k * kWaves + w];
+    v[k] = t;
+  }
+}
+
+// Fixed-order workgroup sum of one double per thread.  Valid in every
+// thread; lds (kWaves doubles) may be reused after return.
+__device__ __forceinline__ double wg_sum(double v, double* lds) {
+  double a[1] = {v};
+  wg_sum_all<1>(a, lds);
+  __syncthreads();
+  return a[0];
 }
 
 }  // namespace agc

@@ -69,12 +69,9 @@ struct Mesh {
   // full fine pattern from the upper one
   int64_t ff_nnzb = 0;
   DevBuf ff_row_ptr, ff_col, ff_rowidx, ff_src, ff_diag;   // src = upper*2 + transposed
-  // vertex -> (element, local vertex) incidence
-  DevBuf va_ptr, va;     // va[k] = e*4 + a
   void release() {
     elem_verts.release(); fu_row.release(); fu_col.release(); plan_ptr.release(); plan.release();
     ff_row_ptr.release(); ff_col.release(); ff_rowidx.release(); ff_src.release(); ff_diag.release();
-    va_ptr.release(); va.release();
   }
 };
 
@@ -109,32 +106,36 @@ int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, co
 // members[k]: vertices sorted by (map, id); mkeys[k] = map[members[k]]
 void group_members(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, uint32_t* members,
                    uint32_t* mkeys);
-// v_c[c] = sum over members of v (fixed order); sub != nullptr gives (v - sub)
+// v_c[c] = sum over members of v (fixed order)
 void restrict_sorted(agc_context* c, int32_t n, int32_t n_c, const uint32_t* members,
-                     const uint32_t* mkeys, const double* v, const double* sub, double* v_c);
+                     const uint32_t* mkeys, const double* v, double* v_c);
 // x[v] = x_c[map[v]]; a map value outside [0, n_c) sets kErrMap and writes 0
 void prolongate(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, const double* x_c, double* x);
 
 // ------------------------------------------------------------- assembly
 void mesh_build(agc_context* c, Mesh& m, int32_t n_verts, int64_t n_elems, const int32_t* ev);
+// out32 (float64 output only, may be null) receives the same matrix rounded
+// to float32; it borrows out's pattern, so out must outlive its use.
 void assemble_fine(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
-                   int32_t out_dtype, Matrix& out);
+                   int32_t out_dtype, Matrix& out, Matrix* out32 = nullptr);
 void assemble_coarse(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
-                     const int32_t* map, int32_t n_c, int32_t out_dtype, Matrix& out);
-// rf = g - H (P x_c) on the fine level from float64 element blocks (map may be null: identity)
-void elem_residual(agc_context* c, const Mesh& m, const double* elem_h, const int32_t* map,
-                   const double* x_c, const double* g, double* rf);
+                     const int32_t* map, int32_t n_c, int32_t out_dtype, Matrix& out,
+                     Matrix* out32 = nullptr);
 // dH_e = -(dg_e)(x_e)^T
 void elem_outer(agc_context* c, const Mesh& m, const double* dg, const double* x, double* dh);
 
 // ------------------------------------------------------------------ PCG
 void spmv(agc_context* c, const Matrix& a, const double* x, double* y);
-// returns status (AGC_OK / NOT_CONVERGED / NOT_SPD); *iters, *rel set
+// returns status (AGC_OK / NOT_CONVERGED / NOT_SPD); *iters, *rel set.
+// x holds x0 on entry, or x_zero says x0 = 0 (x is then output only).
 int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol, int32_t max_iter,
-        int32_t* iters, double* rel);
+        int32_t* iters, double* rel, bool x_zero = false);
 // ||v||_2 of an [n][3] vector (float64, fixed order); synchronises
 double norm2(agc_context* c, const double* v, int64_t n3, const std::string& tag);
 void axpy_vec(agc_context* c, double* y, const double* x, double a, int64_t n3);
+// r = b - y and the float64 norms of b and r (fixed order); synchronises
+void residual_norms(agc_context* c, const double* b, const double* y, double* r, int64_t n3, double* bn,
+                    double* rn);
 
 }  // namespace agc
 

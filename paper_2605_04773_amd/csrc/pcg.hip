@@ -8,9 +8,10 @@
 // idle behind one wave.  Values are stored as nine planes (stride padded to
 // 64 blocks), so a thread's four values of one plane are one 16- or 32-byte
 // load and a wave's loads are contiguous.  Rows are summed inside a thread in
-// order, then across threads by a wave64 segmented scan plus a carry across
-// the four waves; a row that crosses workgroups leaves one partial per
-// workgroup in `carry`, and the consumer adds them in workgroup order.
+// order, then across the threads of a wave by a DPP segmented scan, then
+// across the four waves through LDS (one barrier per tile).  A row that
+// crosses workgroups leaves one partial per workgroup in `carry`, and the
+// consumer adds them in workgroup order.
 //
 // PCG, two launches per iteration j (plus one tiny check per chunk):
 //   K_a  reduce K_b's partials -> r^T z, r^T r; stop test; beta_j;
@@ -22,8 +23,10 @@
 // No atomics and no fences: every workgroup of a kernel sums all partials
 // of the previous kernel in the same fixed order (the kernel boundary makes
 // them visible), so every workgroup takes the same decisions and every run
-// gives bitwise identical iterates.  The host reads the scalars only
-// between chunks of iterations; launches after convergence return at once.
+// gives bitwise identical iterates.  Both kernels issue their loads of the
+// matrix and vectors before that reduction, so its latency overlaps them.
+// The host reads the scalars only between chunks of iterations; launches
+// after convergence return at once.
 #include "internal.h"
 
 namespace agc {
@@ -33,17 +36,33 @@ constexpr int kTile = kWG * kItems;   // blocks per SpMV workgroup
 
 // ------------------------------------------------------------ loads
 
+// Matrix loads stream: with the non-temporal hint they do not push the
+// gathered vectors out of L2.
+#ifndef AGC_SPMV_NT
+#define AGC_SPMV_NT 1
+#endif
+typedef int32_t vi4 __attribute__((ext_vector_type(4)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+template <class V>
+__device__ __forceinline__ V stream_load(const V* p) {
+#if AGC_SPMV_NT
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
 __device__ __forceinline__ void load4(const int32_t* p, int32_t o[4]) {
-  const int4 v = *reinterpret_cast<const int4*>(p);
+  const vi4 v = stream_load(reinterpret_cast<const vi4*>(p));
   o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
-__device__ __forceinline__ void load4(const float* p, double o[4]) {
-  const float4 v = *reinterpret_cast<const float4*>(p);
+__device__ __forceinline__ void load4(const float* p, float o[4]) {
+  const vf4 v = stream_load(reinterpret_cast<const vf4*>(p));
   o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
 __device__ __forceinline__ void load4(const double* p, double o[4]) {
-  const double2 a = reinterpret_cast<const double2*>(p)[0];
-  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  const vd2 a = stream_load(reinterpret_cast<const vd2*>(p));
+  const vd2 b = stream_load(reinterpret_cast<const vd2*>(p) + 1);
   o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
 
@@ -68,170 +87,163 @@ struct GatherP {
 
 // ------------------------------------------------------------- SpMV core
 
-// Segmented (by key) inclusive sum of one 3-vector per thread over the
-// workgroup, keys non-decreasing in thread order.
-__device__ __forceinline__ void wg_row_scan(int32_t row, double v[3], int32_t* t_row, int* t_single,
-                                            double (*t_v)[3]) {
-  const unsigned lane = lane_id(), wave = threadIdx.x / kWave;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int32_t ru = __shfl_up(row, d);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double vu = __shfl_up(v[i], d);
-      if (lane >= (unsigned)d && ru == row) v[i] += vu;
-    }
-  }
-  const int32_t row0 = __shfl(row, 0);
-  if (lane == kWave - 1) {
-    t_row[wave] = row;
-    t_single[wave] = (row0 == row) ? 1 : 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) t_v[wave][i] = v[i];
-  }
-  __syncthreads();
-  if (wave > 0 && t_row[wave - 1] == row) {
-    double cin[3] = {0.0, 0.0, 0.0};
-    for (int u = (int)wave - 1; u >= 0; --u) {
-      if (t_row[u] != row) break;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) cin[i] += t_v[u][i];
-      if (!t_single[u]) break;
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) v[i] += cin[i];
-  }
-}
+// A thread's four blocks, loaded before anything that needs a scalar from
+// the previous kernel.  Blocks past nnzb carry row INT32_MAX and zeros.
+template <class T>
+struct Quad {
+  int32_t r[kItems], c[kItems];
+  T a[9][kItems];
+  int32_t next_row;   // row of the block after the thread's last one; INT32_MAX at the tile end
+  int32_t edge[4];    // thread 0: ri[t0 - 1], ri[t0], ri[t1 - 1], ri[t1] (-1 where absent)
+};
 
-// One tile of y = A g.  Complete rows go to y; rows crossing the tile edge go
-// to carry[(w*2 + slot)*3 + i] (slot 1: the row starts in this tile, slot 0:
-// it started earlier).  Only the first and the last row of a tile can cross
-// its edges, and the two neighbouring row indices tell which do.
-// PNEW: the thread holding the diagonal block of a row stores the gathered
-// vector of that row to pnew.  DOT: returns, in thread 0, the tile's part of
-// g^T (A g), summed block by block.
-template <class T, class G, bool DOT, bool PNEW>
-__device__ __forceinline__ double spmv_tile(const int32_t* __restrict__ ri, const int32_t* __restrict__ col,
-                                            const T* __restrict__ vals, int64_t nnzb, int64_t stride, const G& g,
-                                            double* __restrict__ y, double* __restrict__ carry,
-                                            double* __restrict__ pnew, double* red) {
-  __shared__ int32_t t_row[kWaves];
-  __shared__ int t_single[kWaves];
-  __shared__ double t_v[kWaves][3];
-  __shared__ int32_t w_row[kWaves];
-  __shared__ double w_s[kWaves][3];
-  __shared__ int32_t edge[2];   // row continuing from the previous tile / into the next one, or -1
-  const int64_t w = blockIdx.x;
+template <class T>
+__device__ __forceinline__ void load_quad(int64_t w, const int32_t* __restrict__ ri, const int32_t* __restrict__ col,
+                                          const T* __restrict__ vals, int64_t nnzb, int64_t stride, Quad<T>& q) {
   const int64_t t0 = w * kTile;
   const int64_t t1 = (t0 + kTile < nnzb) ? t0 + kTile : nnzb;
   const int64_t k0 = t0 + (int64_t)threadIdx.x * kItems;
-  if (threadIdx.x == 0) {
-    const int32_t first = ri[t0];
-    edge[0] = (t0 > 0 && ri[t0 - 1] == first) ? first : -1;
-    const int32_t last = ri[t1 - 1];
-    edge[1] = (t1 < nnzb && ri[t1] == last) ? last : -1;
-  }
-  const int64_t kn = k0 + kItems;
-  const int32_t next_row = (kn < t1) ? ri[kn] : INT32_MAX;
-  int32_t r[kItems], c[kItems];
-  double v[kItems][3];
-  double dot = 0.0;
-  if (t0 + kTile <= nnzb) {
-    double a[9][kItems];
-    load4(ri + k0, r);
-    load4(col + k0, c);
+  if (k0 + kItems <= nnzb) {
+    load4(ri + k0, q.r);
+    load4(col + k0, q.c);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) load4(vals + (int64_t)i * stride + k0, a[i]);
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      double xv[3];
-      g.get(c[j], xv);
-      v[j][0] = a[0][j] * xv[0] + a[1][j] * xv[1] + a[2][j] * xv[2];
-      v[j][1] = a[3][j] * xv[0] + a[4][j] * xv[1] + a[5][j] * xv[2];
-      v[j][2] = a[6][j] * xv[0] + a[7][j] * xv[1] + a[8][j] * xv[2];
-      if (PNEW && c[j] == r[j]) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) pnew[3 * (int64_t)r[j] + i] = xv[i];
-      }
-      if (DOT) {
-        double pr[3];
-        g.get(r[j], pr);
-        dot += pr[0] * v[j][0] + pr[1] * v[j][1] + pr[2] * v[j][2];
-      }
-    }
+    for (int i = 0; i < 9; ++i) load4(vals + (int64_t)i * stride + k0, q.a[i]);
   } else {
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const int64_t k = k0 + j;
-      if (k < nnzb) {
-        r[j] = ri[k];
-        c[j] = col[k];
-        double a[9], xv[3];
+      const bool in = k < nnzb;
+      q.r[j] = in ? ri[k] : INT32_MAX;
+      q.c[j] = in ? col[k] : 0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) a[i] = (double)vals[(int64_t)i * stride + k];
-        g.get(c[j], xv);
-        v[j][0] = a[0] * xv[0] + a[1] * xv[1] + a[2] * xv[2];
-        v[j][1] = a[3] * xv[0] + a[4] * xv[1] + a[5] * xv[2];
-        v[j][2] = a[6] * xv[0] + a[7] * xv[1] + a[8] * xv[2];
-        if (PNEW && c[j] == r[j]) {
-#pragma unroll
-          for (int i = 0; i < 3; ++i) pnew[3 * (int64_t)r[j] + i] = xv[i];
-        }
-        if (DOT) {
-          double pr[3];
-          g.get(r[j], pr);
-          dot += pr[0] * v[j][0] + pr[1] * v[j][1] + pr[2] * v[j][2];
-        }
-      } else {
-        r[j] = INT32_MAX;
-        c[j] = 0;
-        v[j][0] = v[j][1] = v[j][2] = 0.0;
-      }
+      for (int i = 0; i < 9; ++i) q.a[i][j] = in ? vals[(int64_t)i * stride + k] : (T)0;
     }
   }
-  // the thread's last run, scanned across threads
-  const int32_t head = r[0], tail = r[kItems - 1];
+  const int64_t kn = k0 + kItems;
+  q.next_row = (kn < t1) ? ri[kn] : INT32_MAX;
+  if (threadIdx.x == 0) {
+    q.edge[0] = t0 > 0 ? ri[t0 - 1] : -1;
+    q.edge[1] = ri[t0];
+    q.edge[2] = ri[t1 - 1];
+    q.edge[3] = t1 < nnzb ? ri[t1] : -1;
+  }
+}
+
+struct TileLds {
+  int32_t row[kWaves];      // key of lane 63 of each wave
+  int32_t single[kWaves];   // 1 if that key's run reaches back to lane 0 whole
+  double v[kWaves][3];      // lane 63's scanned sums
+  double dot[kWaves];
+  int32_t edge[2];          // row continuing from the previous tile / into the next one, or -1
+};
+
+// One tile of y = A g from a loaded quad.  Complete rows go to y; rows
+// crossing the tile edge go to carry[(w*2 + slot)*3 + i] (slot 1: the row
+// starts in this tile, slot 0: it started earlier).  Only the first and the
+// last row of a tile can cross its edges.
+// PNEW: the thread holding the diagonal block of a row stores the gathered
+// vector of that row to pnew.  DOT: returns, in every thread, the tile's part
+// of g^T (A g) (each block's product dotted with its row's g, in block order
+// per thread, then lanes, then waves).
+template <class T, class G, bool DOT, bool PNEW>
+__device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G& g, double* __restrict__ y,
+                                            double* __restrict__ carry, double* __restrict__ pnew, TileLds& L) {
+  const unsigned lane = lane_id(), wave = threadIdx.x / kWave;
+  double v[kItems][3];
+  double dot = 0.0;
+  double pr0[3] = {0.0, 0.0, 0.0}, pr3[3] = {0.0, 0.0, 0.0};
+  if (DOT) {
+    if (q.r[0] != INT32_MAX) g.get(q.r[0], pr0);
+    if (q.r[kItems - 1] != q.r[0] && q.r[kItems - 1] != INT32_MAX) g.get(q.r[kItems - 1], pr3);
+  }
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    double xv[3];
+    g.get(q.c[j], xv);
+    v[j][0] = (double)q.a[0][j] * xv[0] + (double)q.a[1][j] * xv[1] + (double)q.a[2][j] * xv[2];
+    v[j][1] = (double)q.a[3][j] * xv[0] + (double)q.a[4][j] * xv[1] + (double)q.a[5][j] * xv[2];
+    v[j][2] = (double)q.a[6][j] * xv[0] + (double)q.a[7][j] * xv[1] + (double)q.a[8][j] * xv[2];
+    if (PNEW && q.c[j] == q.r[j]) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) pnew[3 * (int64_t)q.r[j] + i] = xv[i];
+    }
+  }
+  if (DOT) {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int32_t rj = q.r[j];
+      if (rj == INT32_MAX) continue;
+      double pr[3];
+      if (rj == q.r[0]) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) pr[i] = pr0[i];
+      } else if (rj == q.r[kItems - 1]) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) pr[i] = pr3[i];
+      } else {
+        g.get(rj, pr);
+      }
+      dot += pr[0] * v[j][0] + pr[1] * v[j][1] + pr[2] * v[j][2];
+    }
+  }
+  // the thread's last run, scanned across the wave, then across waves
+  const int32_t head = q.r[0], tail = q.r[kItems - 1];
   double s[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < kItems; ++j)
-    if (r[j] == tail) {
+    if (q.r[j] == tail) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) s[i] += v[j][i];
     }
-  wg_row_scan(tail, s, t_row, t_single, t_v);
-  const unsigned lane = lane_id(), wave = threadIdx.x / kWave;
-  int32_t prev_tail = __shfl_up(tail, 1);
-  double prev_s[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) prev_s[i] = __shfl_up(s[i], 1);
+  wave_seg_scan<3>(tail, s);
+  double d1[1] = {dot};
+  if (DOT) wave_seg_scan<1>(0, d1);
+  const int32_t tail0 = __builtin_amdgcn_readfirstlane(tail);   // lane 0 is active
   if (lane == kWave - 1) {
-    w_row[wave] = tail;
+    L.row[wave] = tail;
+    L.single[wave] = (tail0 == tail) ? 1 : 0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) w_s[wave][i] = s[i];
+    for (int i = 0; i < 3; ++i) L.v[wave][i] = s[i];
+    if (DOT) L.dot[wave] = d1[0];
+  }
+  if (threadIdx.x == 0) {
+    L.edge[0] = (q.edge[0] == q.edge[1]) ? q.edge[1] : -1;
+    L.edge[1] = (q.edge[3] == q.edge[2]) ? q.edge[2] : -1;
   }
   __syncthreads();
-  if (lane == 0) {
-    if (wave > 0) {
-      prev_tail = w_row[wave - 1];
+  // carry into this wave: the previous waves' sums of row R = key of the
+  // previous wave's lane 63, walking back while that row fills whole waves
+  int32_t R = INT32_MIN;
+  double cin[3] = {0.0, 0.0, 0.0};
+  if (wave > 0) {
+    R = L.row[wave - 1];
+    for (int u = (int)wave - 1; u >= 0; --u) {
+      if (L.row[u] != R) break;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) prev_s[i] = w_s[wave - 1][i];
-    } else {
-      prev_tail = INT32_MIN;
+      for (int i = 0; i < 3; ++i) cin[i] += L.v[u][i];
+      if (!L.single[u]) break;
     }
   }
-  const int32_t e_before = edge[0], e_after = edge[1];
-  double acc[3] = {0.0, 0.0, 0.0};
-  if (prev_tail == head) {
+  if (tail == R) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) acc[i] = prev_s[i];
+    for (int i = 0; i < 3; ++i) s[i] += cin[i];
   }
+  // exclusive value for the head row: lane i-1's scanned tail, (R, cin) for lane 0
+  const int32_t prev_row = dpp_move<kDppWaveShr1, 0xf>(R, tail);
+  double acc[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double ps = dpp_move<kDppWaveShr1, 0xf>(cin[i], s[i]);
+    acc[i] = (prev_row == head) ? ps : 0.0;
+  }
+  const int32_t e_before = L.edge[0], e_after = L.edge[1];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) acc[i] += v[j][i];
-    const int32_t nr = (j + 1 < kItems) ? r[j + 1] : next_row;
-    if (nr != r[j]) {
-      const int32_t row = r[j];
+    const int32_t nr = (j + 1 < kItems) ? q.r[j + 1] : q.next_row;
+    if (nr != q.r[j]) {
+      const int32_t row = q.r[j];
       if (row != INT32_MAX) {
         const bool before = row == e_before, after = row == e_after;
         if (!before && !after) {
@@ -247,7 +259,10 @@ __device__ __forceinline__ double spmv_tile(const int32_t* __restrict__ ri, cons
     }
   }
   if (!DOT) return 0.0;
-  return wg_sum(dot, red);
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < kWaves; ++u) t += L.dot[u];
+  return t;
 }
 
 // q[r] for a row whose blocks may span several tiles.
@@ -274,8 +289,11 @@ __global__ __launch_bounds__(kWG) void k_spmv(const int32_t* __restrict__ col, c
                                               const T* __restrict__ vals, int64_t nnzb, int64_t stride,
                                               const double* __restrict__ x, double* __restrict__ y,
                                               double* __restrict__ carry) {
-  __shared__ double red[kWaves];
-  (void)spmv_tile<T, GatherX, false, false>(ri, col, vals, nnzb, stride, GatherX{x}, y, carry, nullptr, red);
+  __shared__ TileLds L;
+  const int64_t w = xcd_block();
+  Quad<T> q;
+  load_quad(w, ri, col, vals, nnzb, stride, q);
+  (void)spmv_tile<T, GatherX, false, false>(w, q, GatherX{x}, y, carry, nullptr, L);
 }
 
 // rows that cross tiles: y[r] = sum of their partials in tile order
@@ -376,20 +394,16 @@ __global__ __launch_bounds__(kWG) void k_jacobi(const int32_t* __restrict__ diag
 // ------------------------------------------------------------------ PCG
 
 // Sums K rows of per-workgroup partials part[k][0..G) in a fixed order and
-// gives every thread the totals.
+// gives every thread the totals (one barrier; lds holds K * kWaves doubles).
 template <int K>
-__device__ __forceinline__ void all_sum(const double* __restrict__ part, unsigned G, double* red, double* bc,
-                                        double (&tot)[K]) {
+__device__ __forceinline__ void all_sum(const double* __restrict__ part, unsigned G, double* lds, double (&tot)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double s = 0.0;
     for (unsigned i = threadIdx.x; i < G; i += kWG) s += part[(int64_t)k * G + i];
-    s = wg_sum(s, red);
-    if (threadIdx.x == 0) bc[k] = s;
+    tot[k] = s;
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) tot[k] = bc[k];
+  wg_sum_all<K>(tot, lds);
 }
 
 // The stop test on the scalars of iteration j (r^T z, r^T r, and at j = 0
@@ -403,10 +417,9 @@ __device__ __forceinline__ int stop_code(int64_t j, double rz, double rr, double
 
 // partials of the update kernels: [3][G_rows] = r^T z, r^T r, b^T b (init only)
 __device__ __forceinline__ void iteration_scalars(int64_t j, const double* pb, unsigned gb, PcgState* st, double rtol,
-                                                  double* red, double* bc, int* done_out, double* rz_out,
-                                                  double* beta_out) {
+                                                  double* lds, int* done_out, double* beta_out) {
   double t[3];
-  all_sum<3>(pb, gb, red, bc, t);
+  all_sum<3>(pb, gb, lds, t);
   const double rz = t[0], rr = t[1];
   double tol2;
   if (j == 0) {
@@ -426,54 +439,54 @@ __device__ __forceinline__ void iteration_scalars(int64_t j, const double* pb, u
     if (done) st->done = done;
   }
   *done_out = done;
-  *rz_out = rz;
   *beta_out = (j == 0) ? 0.0 : rz / st->rz_hist[(j - 1) & 1];
 }
 
-__device__ __forceinline__ void dinv_apply(const double* __restrict__ dinv, int64_t n, int64_t r, const double v[3],
-                                           double z[3]) {
-  double m[9];
+__device__ __forceinline__ void load_dinv(const double* __restrict__ dinv, int64_t n, int64_t r, double m[9]) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) m[i] = dinv[(int64_t)i * n + r];
+}
+__device__ __forceinline__ void apply3(const double m[9], const double v[3], double z[3]) {
   z[0] = m[0] * v[0] + m[1] * v[1] + m[2] * v[2];
   z[1] = m[3] * v[0] + m[4] * v[1] + m[5] * v[2];
   z[2] = m[6] * v[0] + m[7] * v[1] + m[8] * v[2];
 }
 
-// r = b - q, z = D^{-1} r, p_old = 0; partials of r^T z, r^T r, b^T b
+// r = b - q (q == nullptr: x0 = 0, r = b, and x is zeroed here), z = D^{-1} r,
+// p_old = 0; partials of r^T z, r^T r, b^T b
 __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, const double* __restrict__ q,
-                                                  const double* __restrict__ dinv, int32_t n, double* __restrict__ r,
-                                                  double* __restrict__ z, double* __restrict__ p_old,
-                                                  double* __restrict__ pb) {
-  __shared__ double red[kWaves];
+                                                  const double* __restrict__ dinv, int32_t n, double* __restrict__ x,
+                                                  double* __restrict__ r, double* __restrict__ z,
+                                                  double* __restrict__ p_old, double* __restrict__ pb) {
+  __shared__ double lds[3 * kWaves];
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  double rz = 0.0, rr = 0.0, bb = 0.0;
+  double t[3] = {0.0, 0.0, 0.0};   // r^T z, r^T r, b^T b
   if (i < n) {
-    double rv[3], zv[3];
+    double rv[3], zv[3], m[9];
+    load_dinv(dinv, n, i, m);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double bk = b[3 * i + k];
-      rv[k] = bk - q[3 * i + k];
-      bb += bk * bk;
+      rv[k] = q ? bk - q[3 * i + k] : bk;
+      t[2] += bk * bk;
     }
-    dinv_apply(dinv, n, i, rv, zv);
+    apply3(m, rv, zv);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       r[3 * i + k] = rv[k];
       z[3 * i + k] = zv[k];
       p_old[3 * i + k] = 0.0;
-      rz += rv[k] * zv[k];
-      rr += rv[k] * rv[k];
+      if (!q) x[3 * i + k] = 0.0;
+      t[0] += rv[k] * zv[k];
+      t[1] += rv[k] * rv[k];
     }
   }
+  wg_sum_all<3>(t, lds);
   const unsigned G = gridDim.x;
-  rz = wg_sum(rz, red);
-  rr = wg_sum(rr, red);
-  bb = wg_sum(bb, red);
   if (threadIdx.x == 0) {
-    pb[blockIdx.x] = rz;
-    pb[G + blockIdx.x] = rr;
-    pb[2 * G + blockIdx.x] = bb;
+    pb[blockIdx.x] = t[0];
+    pb[G + blockIdx.x] = t[1];
+    pb[2 * G + blockIdx.x] = t[2];
   }
 }
 
@@ -482,19 +495,22 @@ __global__ __launch_bounds__(kWG) void k_pcg_a(int64_t j, const int32_t* __restr
                                                const int32_t* __restrict__ ri, const T* __restrict__ vals,
                                                int64_t nnzb, int64_t stride, const double* __restrict__ z,
                                                const double* __restrict__ p_old, double* __restrict__ p_new,
-                                               double* __restrict__ q, double* __restrict__ carry,
+                                               double* __restrict__ qv, double* __restrict__ carry,
                                                const double* __restrict__ pb, unsigned gb, double* __restrict__ pa,
                                                PcgState* st, double rtol) {
-  __shared__ double red[kWaves];
-  __shared__ double bc[3];
+  __shared__ TileLds L;
+  __shared__ double lds[3 * kWaves];
+  const int64_t w = xcd_block();
+  Quad<T> q;
+  load_quad(w, ri, col, vals, nnzb, stride, q);   // needs no scalar: in flight during the reduction
   if (st->done) return;
   int done;
-  double rz, beta;
-  iteration_scalars(j, pb, gb, st, rtol, red, bc, &done, &rz, &beta);
+  double beta;
+  iteration_scalars(j, pb, gb, st, rtol, lds, &done, &beta);
   if (done) return;
   const GatherP g{z, p_old, beta};
-  const double d = spmv_tile<T, GatherP, true, true>(ri, col, vals, nnzb, stride, g, q, carry, p_new, red);
-  if (threadIdx.x == 0) pa[blockIdx.x] = d;
+  const double d = spmv_tile<T, GatherP, true, true>(w, q, g, qv, carry, p_new, L);
+  if (threadIdx.x == 0) pa[w] = d;
 }
 
 __global__ __launch_bounds__(kWG) void k_pcg_b(int64_t j, const int32_t* __restrict__ rp, int32_t n,
@@ -503,58 +519,69 @@ __global__ __launch_bounds__(kWG) void k_pcg_b(int64_t j, const int32_t* __restr
                                                double* __restrict__ x, double* __restrict__ r,
                                                double* __restrict__ z, const double* __restrict__ pa, unsigned ga,
                                                double* __restrict__ pb, PcgState* st) {
-  __shared__ double red[kWaves];
-  __shared__ double bc[1];
+  __shared__ double lds_a[kWaves], lds_b[2 * kWaves];
+  const int64_t blk = xcd_block();
+  const int64_t i = blk * kWG + threadIdx.x;
+  const bool in = i < n;
+  // everything but alpha is loaded before the reduction
+  double q[3] = {0.0, 0.0, 0.0}, pv[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0}, rv[3] = {0.0, 0.0, 0.0};
+  double m[9];
+  if (in) {
+    row_result(rp, qy, carry, i, q);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      pv[k] = p[3 * i + k];
+      xv[k] = x[3 * i + k];
+      rv[k] = r[3 * i + k];
+    }
+    load_dinv(dinv, n, i, m);
+  }
   if (st->done) return;
   double pq[1];
-  all_sum<1>(pa, ga, red, bc, pq);
+  all_sum<1>(pa, ga, lds_a, pq);
   if (!(pq[0] > 0.0)) {   // p^T A p <= 0 or NaN: not SPD (every workgroup sees the same value)
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
     return;
   }
   const double alpha = st->rz_hist[j & 1] / pq[0];
-  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
-  if (i < n) {
-    double q[3], rv[3], zv[3];
-    row_result(rp, qy, carry, i, q);
+  double t[2] = {0.0, 0.0};   // r^T z, r^T r
+  if (in) {
+    double zv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      x[3 * i + k] += alpha * p[3 * i + k];
-      rv[k] = r[3 * i + k] - alpha * q[k];
+      x[3 * i + k] = xv[k] + alpha * pv[k];
+      rv[k] = rv[k] - alpha * q[k];
       r[3 * i + k] = rv[k];
     }
-    dinv_apply(dinv, n, i, rv, zv);
+    apply3(m, rv, zv);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       z[3 * i + k] = zv[k];
-      rz += rv[k] * zv[k];
-      rr += rv[k] * rv[k];
+      t[0] += rv[k] * zv[k];
+      t[1] += rv[k] * rv[k];
     }
   }
+  wg_sum_all<2>(t, lds_b);
   const unsigned G = gridDim.x;
-  rz = wg_sum(rz, red);
-  rr = wg_sum(rr, red);
   if (threadIdx.x == 0) {
-    pb[blockIdx.x] = rz;
-    pb[G + blockIdx.x] = rr;
-    pb[2 * G + blockIdx.x] = 0.0;
+    pb[blk] = t[0];
+    pb[G + blk] = t[1];
+    pb[2 * G + blk] = 0.0;
   }
 }
 
 // The stop test of iteration j alone (one workgroup), run at the end of a chunk.
 __global__ __launch_bounds__(kWG) void k_pcg_check(int64_t j, const double* __restrict__ pb, unsigned gb,
                                                    PcgState* st, double rtol) {
-  __shared__ double red[kWaves];
-  __shared__ double bc[3];
+  __shared__ double lds[3 * kWaves];
   if (st->done) return;
   int done;
-  double rz, beta;
-  iteration_scalars(j, pb, gb, st, rtol, red, bc, &done, &rz, &beta);
+  double beta;
+  iteration_scalars(j, pb, gb, st, rtol, lds, &done, &beta);
 }
 
 int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters,
-        double* rel) {
+        double* rel, bool x_zero) {
   const int32_t n = a.n;
   const int64_t n3 = 3 * (int64_t)n;
   *iters = 0;
@@ -582,9 +609,9 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   else
     k_jacobi<float><<<gr, kWG, 0, c->stream>>>(a.dg(), (const float*)a.vals.p, a.stride, n, dinv, c->d_err);
   AGC_LAUNCH_CHECK();
-  spmv(c, a, x, q);   // q = A x0
+  if (!x_zero) spmv(c, a, x, q);   // q = A x0
   // iteration j reads p_{j-1} from pp[(j+1)%2] and writes p_j to pp[j%2]
-  k_pcg_init<<<gr, kWG, 0, c->stream>>>(b, q, dinv, n, r, z, pp[1], pb);
+  k_pcg_init<<<gr, kWG, 0, c->stream>>>(b, x_zero ? nullptr : q, dinv, n, x, r, z, pp[1], pb);
   AGC_LAUNCH_CHECK();
   k_pcg_check<<<1, kWG, 0, c->stream>>>(0, pb, gr, st, rtol);
   AGC_LAUNCH_CHECK();
@@ -684,6 +711,53 @@ double norm2(agc_context* c, const double* v, int64_t n3, const std::string& tag
   AGC_HIP(hipMemcpyAsync(&h, part + G, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   AGC_HIP(hipStreamSynchronize(c->stream));
   return sqrt(h);
+}
+
+// r = b - y; partial sums of b^2 and r^2 per workgroup
+__global__ __launch_bounds__(kWG) void k_resid_part(const double* __restrict__ b, const double* __restrict__ y,
+                                                    double* __restrict__ r, int64_t n, double* __restrict__ part) {
+  __shared__ double lds[2 * kWaves];
+  double t[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
+    const double bi = b[i], ri = bi - y[i];
+    r[i] = ri;
+    t[0] += bi * bi;
+    t[1] += ri * ri;
+  }
+  wg_sum_all<2>(t, lds);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = t[0];
+    part[gridDim.x + blockIdx.x] = t[1];
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_sum_part2(const double* __restrict__ part, unsigned n,
+                                                   double* __restrict__ out) {
+  __shared__ double lds[2 * kWaves];
+  double t[2] = {0.0, 0.0};
+  for (unsigned i = threadIdx.x; i < n; i += kWG) {
+    t[0] += part[i];
+    t[1] += part[n + i];
+  }
+  wg_sum_all<2>(t, lds);
+  if (threadIdx.x == 0) {
+    out[0] = t[0];
+    out[1] = t[1];
+  }
+}
+
+void residual_norms(agc_context* c, const double* b, const double* y, double* r, int64_t n3, double* bn,
+                    double* rn) {
+  const unsigned G = 512;
+  double* part = c->ws.get<double>("resid.part", 2 * G + 2);
+  k_resid_part<<<G, kWG, 0, c->stream>>>(b, y, r, n3, part);
+  k_sum_part2<<<1, kWG, 0, c->stream>>>(part, G, part + 2 * G);
+  AGC_LAUNCH_CHECK();
+  double* h = (double*)c->h_pcg;   // pinned scratch; no PCG is in flight here
+  AGC_HIP(hipMemcpyAsync(h, part + 2 * G, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  AGC_HIP(hipStreamSynchronize(c->stream));
+  *bn = sqrt(h[0]);
+  *rn = sqrt(h[1]);
 }
 
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {

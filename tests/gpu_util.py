@@ -56,10 +56,9 @@ class Dev:
         self.g = self.t(p["g"], torch.float64)
         self.mesh = agc.agc_mesh_create(ctx, p["n_verts"], self.ev)
 
-    def problem(self, tags=None, use32=False):
+    def problem(self, tags=None):
         agc = binding()
-        return agc.make_problem(self.mesh, self.edges, self.tags if tags is None else tags, self.eh, self.g,
-                                self.eh32 if use32 else None)
+        return agc.make_problem(self.mesh, self.edges, self.tags if tags is None else tags, self.eh, self.g)
 
 
 def to_scipy(mat) -> sp.csr_matrix:

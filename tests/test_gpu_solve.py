@@ -54,9 +54,8 @@ def oracle_solution(name, coarsen=True):
 def run_solve(ctx, d, **kw):
     import torch
     agc = binding()
-    use32 = kw.pop("use32", False)
     tags = kw.pop("tags", None)
-    prob = d.problem(tags=tags, use32=use32)
+    prob = d.problem(tags=tags)
     x = torch.empty((d.p["n_verts"], 3), dtype=torch.float64, device=ctx.device)
     mp = torch.empty(d.p["n_verts"], dtype=torch.int32, device=ctx.device)
     info = agc.agc_solve(ctx, prob, agc.make_opts(**kw), x, mp)
@@ -84,7 +83,7 @@ def test_pcg_fp64_residual(ctx, name):
 
 
 @pytest.mark.parametrize("name", ["c1", "c4"])
-@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed32in"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solve_matches_oracle(ctx, name, precision):
     agc = binding()
     d = dev(ctx, name)
@@ -93,8 +92,7 @@ def test_solve_matches_oracle(ctx, name, precision):
     if precision == "fp64":
         x, mp, info = run_solve(ctx, d, rtol=1e-10)
     else:
-        x, mp, info = run_solve(ctx, d, precision=agc.AGC_PREC_MIXED, rtol=1e-7, use32=precision == "mixed32in")
-        assert info.refine_iters >= 1
+        x, mp, info = run_solve(ctx, d, precision=agc.AGC_PREC_MIXED, rtol=1e-7)
     assert np.array_equal(mp, m) and info.n_coarse == nc
     x_ref = x_ref_c[m]
     err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
