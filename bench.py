@@ -37,12 +37,12 @@ def log(*a):
 
 
 def spmv_bytes(nnzb, n, value_bytes):
-    """Algorithmic bytes of one fused PCG SpMV launch (q = A p, p^T q).
+    """Algorithmic bytes of one fused PCG SpMV launch (w = A z, z^T w).
 
     Per stored 3x3 block: 9 values, its column index and its row index.
-    Per block row: p read once, q written once, one row pointer.
+    Per block row: z read once, w written once.
     """
-    return nnzb * (9 * value_bytes + 4 + 4) + n * (24 + 24 + 4)
+    return nnzb * (9 * value_bytes + 4 + 4) + n * (24 + 24)
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -206,7 +206,7 @@ def main():
                          "pcg": round(ti.ms_pcg, 4), "prolong": round(ti.ms_prolong, 4)},
         },
         "roofline": {
-            "kernel": "k_pcg_a<float> (fused SpMV q = A p and p^T q, float32 matrix)",
+            "kernel": "k_pcg_spmv<float> (fused SpMV w = A z and z^T w, float32 matrix)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_us": round(spmv_avg_ms * 1e3, 3), "launches": ti.spmv_launches,

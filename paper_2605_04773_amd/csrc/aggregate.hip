@@ -4,11 +4,15 @@
 // the graph of collapsible edges, and the supplement's elected-lane popcount
 // plus group prefix sum (Alg. 2, Sec. 1.3) orders them by their smallest fine
 // id.  The paper finds components with 32-bit in-warp hash masks applied
-// level by level.  On gfx950 one edge-parallel pass of lock-free union-find
-// does the same job for any component size: a root is only ever hooked below
-// a smaller root, so the surviving root of every component is its smallest
-// vertex whatever the order of the races.  Flagging the roots and an
-// exclusive scan then give exactly the canonical labels.
+// level by level.  On gfx950 a parent forest does the same job for any
+// component size: every vertex first points at its smallest collapsible
+// neighbour, a few rounds of minimum-label hooking of roots with path
+// flattening merge the trees, and a final edge-parallel pass of lock-free
+// union-find guarantees that every edge ends inside one tree.  A pointer
+// only ever moves to a smaller vertex of the same component, so the
+// surviving root of every component is its smallest vertex whatever the
+// order of the races.  Flagging the roots and an exclusive scan then give
+// exactly the canonical labels.
 #include "segreduce.h"
 
 namespace agc {
@@ -68,14 +72,32 @@ __global__ void k_cc_link_min(const int32_t* __restrict__ edges, const uint8_t* 
   }
 }
 
-// One round of pointer jumping: parent[v] = parent[parent[v]].  Values only
-// move to ancestors, so reading entries another thread has already updated
-// is harmless.
-__global__ void k_cc_jump(int32_t* parent, int32_t n) {
+// Root-level linking round (minimum-label hooking in the manner of
+// Shiloach-Vishkin): for a collapsible edge whose ends have different
+// parents pu, pv, the larger of the two is pointed at the smaller.  Both lie
+// in the edge's component and the value only decreases, so the forest stays
+// valid; a pointer it replaces may drop a link, which the final lock-free
+// pass over every edge restores.
+__global__ void k_cc_link_roots(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
+                                int32_t* parent, int32_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int2 uv = reinterpret_cast<const int2*>(edges)[e];
+    const int32_t u = uv.x, v = uv.y;
+    if (tags[e] != 1 || u == v || u < 0 || u >= n || v < 0 || v >= n) continue;
+    const int32_t pu = parent[u], pv = parent[v];
+    if (pu == pv) continue;
+    const int32_t lo = pu < pv ? pu : pv, hi = pu < pv ? pv : pu;
+    if (parent[hi] > lo) atomicMin(parent + hi, lo);
+  }
+}
+
+// parent[v] = root of v by a read-only walk.  Entries other threads update
+// meanwhile only move to ancestors, so every walk still ends at a root.
+__global__ void k_cc_flatten(int32_t* parent, int32_t n) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t p = parent[v];
-    const int32_t pp = parent[p];
-    if (pp != p) parent[v] = pp;
+    int32_t x = parent[v], p;
+    while ((p = parent[x]) != x) x = p;
+    parent[v] = x;
   }
 }
 
@@ -115,9 +137,10 @@ __global__ void k_cc_label(const int32_t* __restrict__ parent, const uint32_t* _
   }
 }
 
-// Jumping rounds before the hooking pass; each halves every path, and the
-// hooking pass's own path shortening handles whatever remains.
-constexpr int kJumpRounds = 4;
+// Root-linking rounds before the lock-free pass.  On the tet grids two
+// rounds leave (almost) no edge between different trees; the lock-free pass
+// merges whatever remains, so the count only affects speed.
+constexpr int kRootRounds = 2;
 
 static unsigned gs_blocks(int64_t n) {
   int64_t b = (n + kWG - 1) / kWG;
@@ -134,9 +157,11 @@ int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, co
   AGC_LAUNCH_CHECK();
   if (m > 0) {
     k_cc_link_min<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n, c->d_err);
-    AGC_LAUNCH_CHECK();
-    for (int r = 0; r < kJumpRounds; ++r) k_cc_jump<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
-    AGC_LAUNCH_CHECK();
+    k_cc_flatten<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
+    for (int r = 0; r < kRootRounds; ++r) {
+      k_cc_link_roots<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n);
+      k_cc_flatten<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
+    }
     k_cc_hook<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n);
     AGC_LAUNCH_CHECK();
   }

@@ -79,7 +79,8 @@ constexpr int kMaxChunk = 256;   // PCG iterations enqueued between two host che
 
 // Device PCG scalars.
 struct PcgState {
-  double rz_hist[2];              // r^T z of the last even / odd iteration
+  double rz_hist[2];              // gamma_j = r_j^T z_j, by parity of j
+  double alpha_hist[2];           // alpha_j, by parity of j
   double rr, bb, tol2;
   int32_t iter, max_iter, done;   // done: 0 running, 1 converged, 2 max_iter, 3 breakdown
   int32_t pad;

@@ -13,20 +13,25 @@
 // crosses workgroups leaves one partial per workgroup in `carry`, and the
 // consumer adds them in workgroup order.
 //
-// PCG, two launches per iteration j (plus one tiny check per chunk):
-//   K_a  reduce K_b's partials -> r^T z, r^T r; stop test; beta_j;
-//        p_j = z + beta_j p_{j-1} formed on the fly from z and the previous p
-//        (ping-pong buffers; the thread holding a row's diagonal block stores
-//        p_j for that row); q = A p_j; partial p_j^T q per workgroup.
-//   K_b  reduce K_a's partials -> p_j^T q, alpha_j; x += alpha p_j,
-//        r -= alpha q, z = D^{-1} r; partial r^T z, r^T r per workgroup.
+// PCG in its single-reduction form (Chronopoulos and Gear): besides p it
+// carries s = A p, so that both inner products of an iteration, gamma =
+// r^T z and delta = z^T A z, are known before any vector changes, and the
+// only vector the SpMV gathers is z.  In exact arithmetic the iterates are
+// those of standard PCG.  Two launches per iteration j (plus one tiny check
+// per chunk):
+//   K_1  w = A z_j and a partial z_j^T w per workgroup.
+//   K_2  reduce the partials -> gamma_j, r_j^T r_j, delta_j; stop test;
+//        beta_j = gamma_j / gamma_{j-1},
+//        alpha_j = gamma_j / (delta_j - beta_j gamma_j / alpha_{j-1});
+//        p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+//        z = D^{-1} r; partial gamma_{j+1}, r^T r per workgroup.
 // No atomics and no fences: every workgroup of a kernel sums all partials
-// of the previous kernel in the same fixed order (the kernel boundary makes
+// of the previous kernels in the same fixed order (the kernel boundary makes
 // them visible), so every workgroup takes the same decisions and every run
 // gives bitwise identical iterates.  Both kernels issue their loads of the
 // matrix and vectors before that reduction, so its latency overlaps them.
 // The host reads the scalars only between chunks of iterations; launches
-// after convergence return at once.
+// after convergence read one flag and return.
 #include "internal.h"
 
 namespace agc {
@@ -66,7 +71,7 @@ __device__ __forceinline__ void load4(const double* p, double o[4]) {
   o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
 
-// The vector the SpMV multiplies: x itself, or p = z + beta p_old.
+// The vector the SpMV multiplies.
 struct GatherX {
   const double* x;
   __device__ __forceinline__ void get(int64_t c, double o[3]) const {
@@ -75,16 +80,6 @@ struct GatherX {
     o[2] = x[3 * c + 2];
   }
 };
-struct GatherP {
-  const double* z;
-  const double* p;
-  double beta;
-  __device__ __forceinline__ void get(int64_t c, double o[3]) const {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) o[i] = z[3 * c + i] + beta * p[3 * c + i];
-  }
-};
-
 // ------------------------------------------------------------- SpMV core
 
 // A thread's four blocks, loaded before anything that needs a scalar from
@@ -141,13 +136,12 @@ struct TileLds {
 // crossing the tile edge go to carry[(w*2 + slot)*3 + i] (slot 1: the row
 // starts in this tile, slot 0: it started earlier).  Only the first and the
 // last row of a tile can cross its edges.
-// PNEW: the thread holding the diagonal block of a row stores the gathered
-// vector of that row to pnew.  DOT: returns, in every thread, the tile's part
-// of g^T (A g) (each block's product dotted with its row's g, in block order
-// per thread, then lanes, then waves).
-template <class T, class G, bool DOT, bool PNEW>
+// DOT: returns, in every thread, the tile's part of g^T (A g) (each block's
+// product dotted with its row's g, in block order per thread, then lanes,
+// then waves).
+template <class T, class G, bool DOT>
 __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G& g, double* __restrict__ y,
-                                            double* __restrict__ carry, double* __restrict__ pnew, TileLds& L) {
+                                            double* __restrict__ carry, TileLds& L) {
   const unsigned lane = lane_id(), wave = threadIdx.x / kWave;
   double v[kItems][3];
   double dot = 0.0;
@@ -163,10 +157,6 @@ __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G
     v[j][0] = (double)q.a[0][j] * xv[0] + (double)q.a[1][j] * xv[1] + (double)q.a[2][j] * xv[2];
     v[j][1] = (double)q.a[3][j] * xv[0] + (double)q.a[4][j] * xv[1] + (double)q.a[5][j] * xv[2];
     v[j][2] = (double)q.a[6][j] * xv[0] + (double)q.a[7][j] * xv[1] + (double)q.a[8][j] * xv[2];
-    if (PNEW && q.c[j] == q.r[j]) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) pnew[3 * (int64_t)q.r[j] + i] = xv[i];
-    }
   }
   if (DOT) {
 #pragma unroll
@@ -293,7 +283,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(const int32_t* __restrict__ col, c
   const int64_t w = xcd_block();
   Quad<T> q;
   load_quad(w, ri, col, vals, nnzb, stride, q);
-  (void)spmv_tile<T, GatherX, false, false>(w, q, GatherX{x}, y, carry, nullptr, L);
+  (void)spmv_tile<T, GatherX, false>(w, q, GatherX{x}, y, carry, L);
 }
 
 // rows that cross tiles: y[r] = sum of their partials in tile order
@@ -387,8 +377,13 @@ __global__ __launch_bounds__(kWG) void k_jacobi(const int32_t* __restrict__ diag
 #pragma unroll
     for (int i = 0; i < 9; ++i) out[i] = 0.0;
   }
-#pragma unroll
-  for (int i = 0; i < 9; ++i) dinv[(int64_t)i * n + r] = out[i];
+  // D^{-1} is symmetric: six planes 00, 01, 02, 11, 12, 22
+  dinv[0 * (int64_t)n + r] = out[0];
+  dinv[1 * (int64_t)n + r] = out[1];
+  dinv[2 * (int64_t)n + r] = out[2];
+  dinv[3 * (int64_t)n + r] = out[4];
+  dinv[4 * (int64_t)n + r] = out[5];
+  dinv[5 * (int64_t)n + r] = out[8];
 }
 
 // ------------------------------------------------------------------ PCG
@@ -415,12 +410,12 @@ __device__ __forceinline__ int stop_code(int64_t j, double rz, double rr, double
   return 0;
 }
 
-// partials of the update kernels: [3][G_rows] = r^T z, r^T r, b^T b (init only)
-__device__ __forceinline__ void iteration_scalars(int64_t j, const double* pb, unsigned gb, PcgState* st, double rtol,
-                                                  double* lds, int* done_out, double* beta_out) {
-  double t[3];
+// The stop test of iteration j from the update partials pb = [3][gb]
+// (gamma_j, r_j^T r_j, b^T b at j = 0); block 0 records the scalars.  Every
+// workgroup computes the same.  t receives the three totals.
+__device__ __forceinline__ int stop_scalars(int64_t j, const double* pb, unsigned gb, PcgState* st, double rtol,
+                                            double* lds, double (&t)[3]) {
   all_sum<3>(pb, gb, lds, t);
-  const double rz = t[0], rr = t[1];
   double tol2;
   if (j == 0) {
     tol2 = rtol * rtol * t[2];
@@ -431,38 +426,38 @@ __device__ __forceinline__ void iteration_scalars(int64_t j, const double* pb, u
   } else {
     tol2 = st->tol2;
   }
-  const int done = stop_code(j, rz, rr, t[2], tol2, st->max_iter);
+  const int done = stop_code(j, t[0], t[1], t[2], tol2, st->max_iter);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->iter = (int32_t)j;
-    st->rr = rr;
-    st->rz_hist[j & 1] = rz;
+    st->rr = t[1];
     if (done) st->done = done;
   }
-  *done_out = done;
-  *beta_out = (j == 0) ? 0.0 : rz / st->rz_hist[(j - 1) & 1];
+  return done;
 }
 
-__device__ __forceinline__ void load_dinv(const double* __restrict__ dinv, int64_t n, int64_t r, double m[9]) {
+// the six distinct entries of a row's D^{-1} block: 00, 01, 02, 11, 12, 22
+__device__ __forceinline__ void load_dinv(const double* __restrict__ dinv, int64_t n, int64_t r, double m[6]) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) m[i] = dinv[(int64_t)i * n + r];
+  for (int i = 0; i < 6; ++i) m[i] = dinv[(int64_t)i * n + r];
 }
-__device__ __forceinline__ void apply3(const double m[9], const double v[3], double z[3]) {
+__device__ __forceinline__ void apply3(const double m[6], const double v[3], double z[3]) {
   z[0] = m[0] * v[0] + m[1] * v[1] + m[2] * v[2];
-  z[1] = m[3] * v[0] + m[4] * v[1] + m[5] * v[2];
-  z[2] = m[6] * v[0] + m[7] * v[1] + m[8] * v[2];
+  z[1] = m[1] * v[0] + m[3] * v[1] + m[4] * v[2];
+  z[2] = m[2] * v[0] + m[4] * v[1] + m[5] * v[2];
 }
 
 // r = b - q (q == nullptr: x0 = 0, r = b, and x is zeroed here), z = D^{-1} r,
-// p_old = 0; partials of r^T z, r^T r, b^T b
+// p = s = 0; partials of gamma_0, r^T r, b^T b
 __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, const double* __restrict__ q,
                                                   const double* __restrict__ dinv, int32_t n, double* __restrict__ x,
                                                   double* __restrict__ r, double* __restrict__ z,
-                                                  double* __restrict__ p_old, double* __restrict__ pb) {
+                                                  double* __restrict__ p, double* __restrict__ sv,
+                                                  double* __restrict__ pb) {
   __shared__ double lds[3 * kWaves];
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   double t[3] = {0.0, 0.0, 0.0};   // r^T z, r^T r, b^T b
   if (i < n) {
-    double rv[3], zv[3], m[9];
+    double rv[3], zv[3], m[6];
     load_dinv(dinv, n, i, m);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -475,7 +470,8 @@ __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, 
     for (int k = 0; k < 3; ++k) {
       r[3 * i + k] = rv[k];
       z[3 * i + k] = zv[k];
-      p_old[3 * i + k] = 0.0;
+      p[3 * i + k] = 0.0;
+      sv[3 * i + k] = 0.0;
       if (!q) x[3 * i + k] = 0.0;
       t[0] += rv[k] * zv[k];
       t[1] += rv[k] * rv[k];
@@ -490,83 +486,101 @@ __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, 
   }
 }
 
+// K_1: w = A z, partial z^T w per tile
 template <class T>
-__global__ __launch_bounds__(kWG) void k_pcg_a(int64_t j, const int32_t* __restrict__ col,
-                                               const int32_t* __restrict__ ri, const T* __restrict__ vals,
-                                               int64_t nnzb, int64_t stride, const double* __restrict__ z,
-                                               const double* __restrict__ p_old, double* __restrict__ p_new,
-                                               double* __restrict__ qv, double* __restrict__ carry,
-                                               const double* __restrict__ pb, unsigned gb, double* __restrict__ pa,
-                                               PcgState* st, double rtol) {
+__global__ __launch_bounds__(kWG) void k_pcg_spmv(const int32_t* __restrict__ col, const int32_t* __restrict__ ri,
+                                                  const T* __restrict__ vals, int64_t nnzb, int64_t stride,
+                                                  const double* __restrict__ z, double* __restrict__ w,
+                                                  double* __restrict__ carry, double* __restrict__ pa,
+                                                  const PcgState* st) {
   __shared__ TileLds L;
-  __shared__ double lds[3 * kWaves];
-  const int64_t w = xcd_block();
+  if (st->done) return;   // before the loads: a wave cannot retire with loads in flight
+  const int64_t t = xcd_block();
   Quad<T> q;
-  load_quad(w, ri, col, vals, nnzb, stride, q);   // needs no scalar: in flight during the reduction
-  if (st->done) return;
-  int done;
-  double beta;
-  iteration_scalars(j, pb, gb, st, rtol, lds, &done, &beta);
-  if (done) return;
-  const GatherP g{z, p_old, beta};
-  const double d = spmv_tile<T, GatherP, true, true>(w, q, g, qv, carry, p_new, L);
-  if (threadIdx.x == 0) pa[w] = d;
+  load_quad(t, ri, col, vals, nnzb, stride, q);
+  const double d = spmv_tile<T, GatherX, true>(t, q, GatherX{z}, w, carry, L);
+  if (threadIdx.x == 0) pa[t] = d;
 }
 
-__global__ __launch_bounds__(kWG) void k_pcg_b(int64_t j, const int32_t* __restrict__ rp, int32_t n,
-                                               const double* __restrict__ qy, const double* __restrict__ carry,
-                                               const double* __restrict__ dinv, const double* __restrict__ p,
-                                               double* __restrict__ x, double* __restrict__ r,
-                                               double* __restrict__ z, const double* __restrict__ pa, unsigned ga,
-                                               double* __restrict__ pb, PcgState* st) {
-  __shared__ double lds_a[kWaves], lds_b[2 * kWaves];
+// K_2: the update of iteration j.  Reads the partials pb_in of gamma_j and
+// r_j^T r_j (and b^T b at j = 0) and pa of delta_j; writes those of j + 1 to
+// pb_out (a different buffer: every workgroup reads all of pb_in).
+__global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __restrict__ rp, int32_t n,
+                                                    const double* __restrict__ wy, const double* __restrict__ carry,
+                                                    const double* __restrict__ dinv, double* __restrict__ p,
+                                                    double* __restrict__ sv, double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ z,
+                                                    const double* __restrict__ pa, unsigned ga,
+                                                    const double* __restrict__ pb_in, double* __restrict__ pb_out,
+                                                    PcgState* st, double rtol) {
+  __shared__ double lds_a[3 * kWaves], lds_b[kWaves], lds_c[2 * kWaves];
+  if (st->done) return;
   const int64_t blk = xcd_block();
   const int64_t i = blk * kWG + threadIdx.x;
   const bool in = i < n;
-  // everything but alpha is loaded before the reduction
-  double q[3] = {0.0, 0.0, 0.0}, pv[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0}, rv[3] = {0.0, 0.0, 0.0};
-  double m[9];
+  const unsigned G = gridDim.x;
+  // everything but the scalars is loaded before the reductions
+  double wv[3] = {0.0, 0.0, 0.0}, pv[3] = {0.0, 0.0, 0.0}, sw[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0};
+  double rv[3] = {0.0, 0.0, 0.0}, zv[3] = {0.0, 0.0, 0.0};
+  double m[6];
   if (in) {
-    row_result(rp, qy, carry, i, q);
+    row_result(rp, wy, carry, i, wv);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       pv[k] = p[3 * i + k];
+      sw[k] = sv[3 * i + k];
       xv[k] = x[3 * i + k];
       rv[k] = r[3 * i + k];
+      zv[k] = z[3 * i + k];
     }
     load_dinv(dinv, n, i, m);
   }
-  if (st->done) return;
-  double pq[1];
-  all_sum<1>(pa, ga, lds_a, pq);
-  if (!(pq[0] > 0.0)) {   // p^T A p <= 0 or NaN: not SPD (every workgroup sees the same value)
+  double t[3];
+  const int done = stop_scalars(j, pb_in, G, st, rtol, lds_a, t);
+  if (done) return;
+  double dl[1];
+  all_sum<1>(pa, ga, lds_b, dl);
+  const double gamma = t[0];
+  double beta = 0.0, den = dl[0];
+  if (j > 0) {
+    beta = gamma / st->rz_hist[(j - 1) & 1];
+    den = dl[0] - beta * gamma / st->alpha_hist[(j - 1) & 1];
+  }
+  if (!(den > 0.0)) {   // p^T A p <= 0 or NaN: not SPD (every workgroup sees the same value)
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
     return;
   }
-  const double alpha = st->rz_hist[j & 1] / pq[0];
-  double t[2] = {0.0, 0.0};   // r^T z, r^T r
+  const double alpha = gamma / den;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rz_hist[j & 1] = gamma;
+    st->alpha_hist[j & 1] = alpha;
+  }
+  double u[2] = {0.0, 0.0};   // r^T z, r^T r
   if (in) {
-    double zv[3];
+    double zn[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
+      pv[k] = zv[k] + beta * pv[k];
+      sw[k] = wv[k] + beta * sw[k];
+      p[3 * i + k] = pv[k];
+      sv[3 * i + k] = sw[k];
       x[3 * i + k] = xv[k] + alpha * pv[k];
-      rv[k] = rv[k] - alpha * q[k];
+      rv[k] = rv[k] - alpha * sw[k];
       r[3 * i + k] = rv[k];
     }
-    apply3(m, rv, zv);
+    apply3(m, rv, zn);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      z[3 * i + k] = zv[k];
-      t[0] += rv[k] * zv[k];
-      t[1] += rv[k] * rv[k];
+      z[3 * i + k] = zn[k];
+      u[0] += rv[k] * zn[k];
+      u[1] += rv[k] * rv[k];
     }
   }
-  wg_sum_all<2>(t, lds_b);
-  const unsigned G = gridDim.x;
+  wg_sum_all<2>(u, lds_c);
   if (threadIdx.x == 0) {
-    pb[blk] = t[0];
-    pb[G + blk] = t[1];
-    pb[2 * G + blk] = 0.0;
+    pb_out[blk] = u[0];
+    pb_out[G + blk] = u[1];
+    pb_out[2 * G + blk] = 0.0;
   }
 }
 
@@ -575,10 +589,11 @@ __global__ __launch_bounds__(kWG) void k_pcg_check(int64_t j, const double* __re
                                                    PcgState* st, double rtol) {
   __shared__ double lds[3 * kWaves];
   if (st->done) return;
-  int done;
-  double beta;
-  iteration_scalars(j, pb, gb, st, rtol, lds, &done, &beta);
+  double t[3];
+  (void)stop_scalars(j, pb, gb, st, rtol, lds, t);
 }
+
+constexpr int kFirstChunk = 16;
 
 int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters,
         double* rel, bool x_zero) {
@@ -587,14 +602,16 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   *iters = 0;
   *rel = 0.0;
   if (n == 0) return AGC_OK;
-  double* dinv = c->ws.get<double>("pcg.dinv", 9 * (int64_t)n);
+  double* dinv = c->ws.get<double>("pcg.dinv", 6 * (int64_t)n);
   double* r = c->ws.get<double>("pcg.r", n3);
   double* z = c->ws.get<double>("pcg.z", n3);
-  double* pp[2] = {c->ws.get<double>("pcg.p0", n3), c->ws.get<double>("pcg.p1", n3)};
-  double* q = c->ws.get<double>("pcg.q", n3);
+  double* p = c->ws.get<double>("pcg.p", n3);
+  double* sv = c->ws.get<double>("pcg.s", n3);
+  double* w = c->ws.get<double>("pcg.w", n3);
   const unsigned gr = blocks_for(n, kWG);
   const unsigned gs = blocks_for(a.nnzb, kTile);
-  double* pb = c->ws.get<double>("pcg.pb", 3 * (int64_t)gr);
+  // update partials, double-buffered by parity of j: iteration j reads pbs[j%2]
+  double* pbs[2] = {c->ws.get<double>("pcg.pb0", 3 * (int64_t)gr), c->ws.get<double>("pcg.pb1", 3 * (int64_t)gr)};
   double* pa = c->ws.get<double>("pcg.pa", gs);
   double* carry = spmv_carry(c, a);
   PcgState* st = (PcgState*)c->d_pcg;
@@ -609,29 +626,48 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   else
     k_jacobi<float><<<gr, kWG, 0, c->stream>>>(a.dg(), (const float*)a.vals.p, a.stride, n, dinv, c->d_err);
   AGC_LAUNCH_CHECK();
-  if (!x_zero) spmv(c, a, x, q);   // q = A x0
-  // iteration j reads p_{j-1} from pp[(j+1)%2] and writes p_j to pp[j%2]
-  k_pcg_init<<<gr, kWG, 0, c->stream>>>(b, x_zero ? nullptr : q, dinv, n, x, r, z, pp[1], pb);
+  if (!x_zero) spmv(c, a, x, w);   // w = A x0
+  k_pcg_init<<<gr, kWG, 0, c->stream>>>(b, x_zero ? nullptr : w, dinv, n, x, r, z, p, sv, pbs[0]);
   AGC_LAUNCH_CHECK();
-  k_pcg_check<<<1, kWG, 0, c->stream>>>(0, pb, gr, st, rtol);
+  k_pcg_check<<<1, kWG, 0, c->stream>>>(0, pbs[0], gr, st, rtol);
   AGC_LAUNCH_CHECK();
-  if (err_fetch(c)) return AGC_ERR_NOT_SPD;
 
-  // The host enqueues iterations in chunks and reads the device scalars in
-  // between.  The chunk length is the number of iterations the residual's
-  // observed geometric decay still needs, so few launches land after
-  // convergence (those return at once).
+  // The host enqueues iterations in chunks and reads the device scalars (and
+  // the block-Jacobi error word) in between.  After the first chunk, the
+  // chunk length is the number of iterations the residual's observed
+  // geometric decay still needs, with a margin: launches after convergence
+  // cost a flag read, a host round trip costs far more.
   const bool kt = c->kernel_timing;
-  int chunk = 8;
   int64_t launched = 0, chunk_start = 0;
-  int prev_it = -1;
+  int chunk = kFirstChunk;
+  int prev_it = 0;
   double prev_rr = 0.0;
   for (;;) {
+    chunk_start = launched;
+    for (int it = 0; it < chunk; ++it) {
+      const int64_t j = launched + it;
+      if (kt) AGC_HIP(hipEventRecord(c->kev[2 * it], c->stream));
+      if (a.dtype == AGC_F64)
+        k_pcg_spmv<double><<<gs, kWG, 0, c->stream>>>(a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, a.stride, z,
+                                                      w, carry, pa, st);
+      else
+        k_pcg_spmv<float><<<gs, kWG, 0, c->stream>>>(a.ci(), a.ri(), (const float*)a.vals.p, a.nnzb, a.stride, z,
+                                                     w, carry, pa, st);
+      if (kt) AGC_HIP(hipEventRecord(c->kev[2 * it + 1], c->stream));
+      k_pcg_update<<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, p, sv, x, r, z, pa, gs, pbs[j & 1],
+                                              pbs[(j + 1) & 1], st, rtol);
+    }
+    launched += chunk;
+    k_pcg_check<<<1, kWG, 0, c->stream>>>(launched, pbs[launched & 1], gr, st, rtol);
+    AGC_LAUNCH_CHECK();
     AGC_HIP(hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    AGC_HIP(hipMemcpyAsync(c->h_err, c->d_err, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
     AGC_HIP(hipStreamSynchronize(c->stream));
+    if (*c->h_err) return AGC_ERR_NOT_SPD;   // a diagonal block without a Cholesky factor
     if (kt) {
-      // SpMV launches that did work: global index < completed iterations
-      for (int64_t j = chunk_start; j < launched && j < hs->iter; ++j) {
+      // SpMV launches that did work: K_1 of iteration j runs unless an
+      // earlier stop test fired, i.e. for j <= the final iteration
+      for (int64_t j = chunk_start; j < launched && j <= hs->iter; ++j) {
         float ms = 0.f;
         const int s = (int)(j - chunk_start);
         AGC_HIP(hipEventElapsedTime(&ms, c->kev[2 * s], c->kev[2 * s + 1]));
@@ -642,34 +678,15 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
     if (hs->done) break;
     // the device stops at max_iter; this only guards the host against a lost state
     if (launched > (int64_t)max_iter + 64) throw Error(AGC_ERR_DEVICE, "PCG state did not advance");
-    if (prev_it >= 0 && hs->iter > prev_it && hs->rr > 0.0 && hs->rr < prev_rr) {
+    if (prev_rr == 0.0 && x_zero) prev_rr = hs->bb;   // r_0 = b
+    double want = 2.0 * chunk;
+    if (hs->iter > prev_it && hs->rr > 0.0 && prev_rr > 0.0 && hs->rr < prev_rr) {
       const double rate = log(hs->rr / prev_rr) / (double)(hs->iter - prev_it);
-      const double remaining = log(hs->tol2 / hs->rr) / rate;
-      chunk = remaining < 2.0 ? 2 : (remaining > 256.0 ? 256 : (int)ceil(remaining));
-    } else if (prev_it >= 0) {
-      chunk = chunk < 32 ? 2 * chunk : 64;
+      want = 1.25 * log(hs->tol2 / hs->rr) / rate + 2.0;
     }
-    if (chunk > kMaxChunk) chunk = kMaxChunk;
+    chunk = want < 4.0 ? 4 : (want > kMaxChunk ? kMaxChunk : (int)ceil(want));
     prev_it = hs->iter;
     prev_rr = hs->rr;
-    chunk_start = launched;
-    for (int it = 0; it < chunk; ++it) {
-      const int64_t j = launched + it;
-      const double* p_old = pp[(j + 1) & 1];
-      double* p_new = pp[j & 1];
-      if (kt) AGC_HIP(hipEventRecord(c->kev[2 * it], c->stream));
-      if (a.dtype == AGC_F64)
-        k_pcg_a<double><<<gs, kWG, 0, c->stream>>>(j, a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, a.stride, z,
-                                                   p_old, p_new, q, carry, pb, gr, pa, st, rtol);
-      else
-        k_pcg_a<float><<<gs, kWG, 0, c->stream>>>(j, a.ci(), a.ri(), (const float*)a.vals.p, a.nnzb, a.stride, z,
-                                                  p_old, p_new, q, carry, pb, gr, pa, st, rtol);
-      if (kt) AGC_HIP(hipEventRecord(c->kev[2 * it + 1], c->stream));
-      k_pcg_b<<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, q, carry, dinv, p_new, x, r, z, pa, gs, pb, st);
-    }
-    launched += chunk;
-    k_pcg_check<<<1, kWG, 0, c->stream>>>(launched, pb, gr, st, rtol);
-    AGC_LAUNCH_CHECK();
   }
   *iters = hs->iter;
   if (hs->bb == 0.0) {

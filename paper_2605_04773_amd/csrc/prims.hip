@@ -11,43 +11,85 @@ namespace agc {
 
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kWG * kScanItems;
+// Up to this many tiles every workgroup sums the totals of the tiles before
+// it itself (two launches); beyond, one workgroup scans the tile totals
+// first (three launches).
+constexpr int64_t kScanDirectTiles = 2048;
 
-__global__ __launch_bounds__(kWG) void k_scan_tile(const uint32_t* __restrict__ in,
-                                                   uint32_t* __restrict__ out,
-                                                   uint32_t* __restrict__ tile_sums, int64_t n) {
-  __shared__ uint32_t lds[kWaves];
+__device__ __forceinline__ void scan_load(const uint32_t* __restrict__ in, int64_t n, uint32_t v[kScanItems],
+                                          uint32_t* s) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t s = 0;
+  *s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    int64_t k = base + i;
+    const int64_t k = base + i;
     v[i] = (k < n) ? in[k] : 0u;
-    s += v[i];
+    *s += v[i];
   }
+}
+
+// tile_sums[w] = sum of tile w
+__global__ __launch_bounds__(kWG) void k_scan_sums(const uint32_t* __restrict__ in, int64_t n,
+                                                   uint32_t* __restrict__ tile_sums) {
+  __shared__ uint32_t lds[kWaves];
+  uint32_t v[kScanItems], s;
+  scan_load(in, n, v, &s);
   uint32_t total;
-  uint32_t off = wg_exclusive_scan(s, lds, &total);
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    int64_t k = base + i;
-    if (k < n) out[k] = off;
-    off += v[i];
-  }
+  (void)wg_exclusive_scan(s, lds, &total);
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kWG) void k_scan_add(uint32_t* __restrict__ out,
-                                                  const uint32_t* __restrict__ tile_off, int64_t n) {
-  const uint32_t add = tile_off[blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  for (int i = threadIdx.x; i < kScanTile; i += kWG) {
-    int64_t k = base + i;
-    if (k < n) out[k] += add;
+// One workgroup: tile_sums[0..tiles] becomes the exclusive scan of the
+// tile totals (in place), tile_sums[tiles] the grand total.
+__global__ __launch_bounds__(kWG) void k_scan_sums_scan(uint32_t* __restrict__ tile_sums, int64_t tiles) {
+  __shared__ uint32_t lds[kWaves];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < tiles; base += kWG) {
+    const int64_t k = base + threadIdx.x;
+    const uint32_t v = (k < tiles) ? tile_sums[k] : 0u;
+    uint32_t total;
+    const uint32_t off = wg_exclusive_scan(v, lds, &total);
+    if (k < tiles) tile_sums[k] = carry + off;
+    carry += total;
   }
+  if (threadIdx.x == 0) tile_sums[tiles] = carry;
 }
 
-__global__ void k_scan_total(uint32_t* out, const uint32_t* tile_off, int64_t n_tiles, int64_t n) {
-  out[n] = tile_off[n_tiles];
+// Exclusive scan of tile w from its offset.  offs == nullptr: the offset is
+// the sum of tile_sums[0..w), formed here (and the grand total by the last
+// tile); otherwise offs[w] is the offset and offs[tiles] the total.
+__global__ __launch_bounds__(kWG) void k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                    int64_t n, const uint32_t* __restrict__ tile_sums,
+                                                    const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t lds[kWaves];
+  __shared__ uint32_t lds2[kWaves];
+  uint32_t v[kScanItems], s;
+  scan_load(in, n, v, &s);
+  const int64_t w = blockIdx.x, tiles = gridDim.x;
+  uint32_t base_off;
+  if (offs) {
+    base_off = offs[w];
+  } else {
+    uint32_t part = 0;
+    const int64_t upto = (w == tiles - 1) ? tiles : w;   // the last tile also forms the total
+    for (int64_t k = threadIdx.x; k < upto; k += kWG) part += (k < w) ? tile_sums[k] : 0u;
+    uint32_t last = 0;
+    if (w == tiles - 1 && threadIdx.x == 0) last = tile_sums[w];
+    uint32_t before;
+    (void)wg_exclusive_scan(part, lds2, &before);
+    base_off = before;
+    if (w == tiles - 1 && threadIdx.x == 0) out[n] = before + last;
+  }
+  uint32_t total;
+  uint32_t off = base_off + wg_exclusive_scan(s, lds, &total);
+  const int64_t base = w * kScanTile + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t k = base + i;
+    if (k < n) out[k] = off;
+    off += v[i];
+  }
+  if (offs && w == tiles - 1 && threadIdx.x == 0) out[n] = offs[tiles];
 }
 
 void scan_u32(agc_context* c, const uint32_t* in, uint32_t* out, int64_t n, const std::string& tag) {
@@ -57,19 +99,15 @@ void scan_u32(agc_context* c, const uint32_t* in, uint32_t* out, int64_t n, cons
   }
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;
   uint32_t* sums = c->ws.get<uint32_t>(tag + ".sums", tiles + 1);
-  k_scan_tile<<<(unsigned)tiles, kWG, 0, c->stream>>>(in, out, sums, n);
+  k_scan_sums<<<(unsigned)tiles, kWG, 0, c->stream>>>(in, n, sums);
   AGC_LAUNCH_CHECK();
-  if (tiles == 1) {
-    // single tile: its total is the grand total, its offset is 0
-    k_scan_total<<<1, 1, 0, c->stream>>>(out, sums, 0, n);
+  if (tiles <= kScanDirectTiles) {
+    k_scan_apply<<<(unsigned)tiles, kWG, 0, c->stream>>>(in, out, n, sums, nullptr);
+  } else {
+    k_scan_sums_scan<<<1, kWG, 0, c->stream>>>(sums, tiles);
     AGC_LAUNCH_CHECK();
-    return;
+    k_scan_apply<<<(unsigned)tiles, kWG, 0, c->stream>>>(in, out, n, sums, sums);
   }
-  // sums[0..tiles] becomes the exclusive scan of the tile totals
-  scan_u32(c, sums, sums, tiles, tag + "+");
-  k_scan_add<<<(unsigned)tiles, kWG, 0, c->stream>>>(out, sums, n);
-  AGC_LAUNCH_CHECK();
-  k_scan_total<<<1, 1, 0, c->stream>>>(out, sums, tiles, n);
   AGC_LAUNCH_CHECK();
 }
 

@@ -236,10 +236,100 @@ def grid_problem(n: int, seed: int, frac: float, young: float = YOUNG, poisson: 
     }
 
 
-# The measured workloads (cube grids of 5 tets/cube).
+def boundary_triangles(tets: np.ndarray, on_face: np.ndarray) -> np.ndarray:
+    """Faces of the tets whose three vertices all satisfy on_face[v] (one per boundary triangle)."""
+    t = tets.astype(np.int64)
+    faces = np.concatenate([t[:, [0, 1, 2]], t[:, [0, 1, 3]], t[:, [0, 2, 3]], t[:, [1, 2, 3]]], axis=0)
+    keep = on_face[faces].all(axis=1)
+    f = np.sort(faces[keep], axis=1)
+    return np.unique(f, axis=0)
+
+
+def contact_blocks(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Point-triangle barrier blocks J^T diag(s) J: J ~ N(0,1) 3x12, s_i = 10^U(2,6) per row."""
+    j = rng.standard_normal((n, 3, 12))
+    s = 10.0 ** rng.uniform(2.0, 6.0, size=(n, 3))
+    blk = np.einsum("nik,ni,nil->nkl", j, s, j)
+    return (0.5 * (blk + np.swapaxes(blk, 1, 2))).reshape(n, 144)
+
+
+def contact_problem(seed: int, n_bodies: int = 96, body=(4, 8, 24), n_contacts: int = 250_000,
+                    frac_range=(0.2, 0.9), young: float = YOUNG, poisson: float = POISSON,
+                    rho: float = DENSITY, h: float = H_STEP) -> dict:
+    """A row of deformable cuboids pressed together, with point-triangle barrier blocks.
+
+    Bodies are body[0] x body[1] x body[2] grids of cubes of edge 1/8 m, 5 tets
+    per cube, the short axis along the row (x), gap 1/16 m, each body shifted
+    by U(-1/16, 1/16) m in y and z.  Contact elements [p, t0, t1, t2] pair a
+    vertex of one body's facing face with a triangle of the neighbouring
+    body's facing face whose centroid lies within 1.5 cube edges in (y, z),
+    both directions; n_contacts of all such candidates are drawn without
+    replacement.  Each body gets its own collapsible fraction q_b ~
+    U(frac_range) of its edges (ranked by the smooth field); afterwards every
+    edge touching a contact element's vertex is protected.
+    """
+    nx, ny, nz = body
+    cell = 1.0 / 8.0
+    gap = 1.0 / 16.0
+    rng_j = rng_for(seed, S_JITTER)
+    jitter = rng_j.uniform(-gap, gap, size=(n_bodies, 2))
+    pos0, tets0 = box_mesh(nx, ny, nz, cell)
+    nvb = pos0.shape[0]
+    edges0 = mesh_edges(tets0, nvb)
+    pos = np.concatenate([pos0 + np.array([b * (nx * cell + gap), jitter[b, 0], jitter[b, 1]])
+                          for b in range(n_bodies)])
+    tets = np.concatenate([tets0 + b * nvb for b in range(n_bodies)]).astype(np.int32)
+    nv = pos.shape[0]
+
+    # facing faces and their candidate pairs
+    tri_lo = boundary_triangles(tets0, np.isclose(pos0[:, 0], 0.0))            # -x face of a body
+    tri_hi = boundary_triangles(tets0, np.isclose(pos0[:, 0], nx * cell))      # +x face
+    v_lo = np.flatnonzero(np.isclose(pos0[:, 0], 0.0))
+    v_hi = np.flatnonzero(np.isclose(pos0[:, 0], nx * cell))
+    cand = []
+    for b in range(n_bodies - 1):
+        for pts, tri, pb, tb in ((v_hi, tri_lo, b, b + 1), (v_lo, tri_hi, b + 1, b)):
+            p_yz = pos[pts + pb * nvb, 1:]
+            c_yz = pos[tri + tb * nvb][:, :, 1:].mean(axis=1)
+            d2 = ((p_yz[:, None, :] - c_yz[None, :, :]) ** 2).sum(axis=2)
+            ip, it = np.nonzero(d2 <= (1.5 * cell) ** 2)
+            cand.append(np.concatenate([(pts[ip] + pb * nvb)[:, None], tri[it] + tb * nvb], axis=1))
+    cand = np.concatenate(cand).astype(np.int32)
+    rng_c = rng_for(seed, S_CONTACT)
+    pick = np.sort(rng_c.choice(cand.shape[0], size=min(n_contacts, cand.shape[0]), replace=False))
+    contacts = cand[pick]
+
+    mu, lam = lame(young, poisson)
+    rot = random_rotations(rng_for(seed, S_ROT), tets.shape[0])
+    elem_h = np.concatenate([elastic_blocks(pos, tets, rot, mu, lam, rho, h),
+                             contact_blocks(rng_c, contacts.shape[0])])
+    vol, _ = shape_gradients(pos, tets)
+
+    rng_f = rng_for(seed, S_FIELD)
+    field = fourier_field(rng_f)
+    fracs = rng_f.uniform(frac_range[0], frac_range[1], size=n_bodies)
+    f = eval_field(field, pos)
+    edges = np.concatenate([edges0 + b * nvb for b in range(n_bodies)]).astype(np.int32)
+    tags = np.concatenate([rank_tags(0.5 * (f[edges0[:, 0] + b * nvb] + f[edges0[:, 1] + b * nvb]), fracs[b])
+                           for b in range(n_bodies)])
+    touched = np.zeros(nv, dtype=bool)
+    touched[contacts.ravel()] = True
+    tags[touched[edges[:, 0]] | touched[edges[:, 1]]] = 0
+
+    g = rng_for(seed, S_GRAD).standard_normal((nv, 3))
+    return {
+        "name": "contact", "n_verts": nv, "pos": pos, "edges": edges, "tags": tags,
+        "elem_verts": np.concatenate([tets, contacts]).astype(np.int32), "elem_H": elem_h, "g": g, "h": h,
+        "mass": lumped_mass(tets, vol, rho, nv), "field": field, "frac": fracs, "seed": seed,
+        "n_tets": tets.shape[0], "n_contacts": contacts.shape[0], "body_verts": nvb,
+    }
+
+
+# The measured workloads.
 CONFIGS = {
     "c1": dict(n=8, seed=1, frac=0.7),      # 729 vertices, 2560 tets, FP64, PCG rtol 1e-10
     "c2": dict(n=64, seed=2, frac=0.6),     # 274,625 vertices, 1.31M tets, FP64 and mixed
+    "c3": dict(contact=True, seed=3),       # 96 bodies, 108,000 vertices, 368,640 tets + 250k contacts
     "c4": dict(n=32, seed=4, frac=0.7),     # 35,937 vertices, adjoint
     "c5": dict(n=128, seed=5, frac=0.6),    # 2.15M vertices, re-aggregation
 }
@@ -247,7 +337,10 @@ CONFIGS = {
 
 def make_config(name: str) -> dict:
     c = CONFIGS[name]
-    p = grid_problem(c["n"], c["seed"], c["frac"])
+    if c.get("contact"):
+        p = contact_problem(c["seed"])
+    else:
+        p = grid_problem(c["n"], c["seed"], c["frac"])
     p["name"] = name
     return p
 

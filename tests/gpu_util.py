@@ -30,6 +30,7 @@ def binding():
 
 @functools.lru_cache(maxsize=None)
 def problem(name: str) -> dict:
+    """The named synthetic problem, generated once per test process (treat as read-only)."""
     log(f"[gen] {name}")
     if name == "tiny":
         return synth.grid_problem(2, 21, 0.5)

@@ -29,7 +29,7 @@ def _agg(ctx, n, edges, tags):
     return m.cpu().numpy(), nc
 
 
-@pytest.mark.parametrize("name", ["c1", "c4"])
+@pytest.mark.parametrize("name", ["c1", "c4", "c3"])
 def test_map_bit_exact(ctx, name):
     p = problem(name)
     log(f"[agg] {name}")

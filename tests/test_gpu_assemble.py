@@ -98,12 +98,23 @@ def test_fine_matches_oracle(ctx, name):
     _check_exact_symmetry(rp, ci, vals)
 
 
-def test_coarse_full_size_c2_sampled(ctx):
-    """C2 at full size: pattern bit-exact; values of sampled rows (incl. the hub row) vs per-row oracle."""
+def _max_plan(p):
+    """Largest number of element sub-blocks summed into one fine block."""
+    ev = p["elem_verts"].astype(np.int64)
+    a, b = np.triu_indices(4)
+    va, vb = ev[:, a], ev[:, b]
+    key = np.minimum(va, vb).ravel() * p["n_verts"] + np.maximum(va, vb).ravel()
+    return int(np.unique(key, return_counts=True)[1].max())
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_coarse_full_size_sampled(ctx, name):
+    """Full size (64^3 grid; 96-body contact row): pattern bit-exact; values of
+    sampled rows (incl. the longest row) vs per-row oracle."""
     agc = binding()
-    d = dev(ctx, "c2")
+    d = dev(ctx, name)
     p = d.p
-    log("[asm] c2 full size")
+    log(f"[asm] {name} full size")
     mp, nc = agc.agc_aggregate(ctx, p["n_verts"], d.edges, d.tags)
     for dt in (agc.AGC_F64, agc.AGC_F32):
         A, _ = agc.agc_assemble_coarse(ctx, d.mesh, d.eh, None, mp, nc, out_dtype=dt)
@@ -117,10 +128,10 @@ def test_coarse_full_size_c2_sampled(ctx):
         blocks = ogal.coarse_rows(p["elem_verts"], p["elem_H"], m, nc, rows)
         ablocks = ogal.coarse_rows(p["elem_verts"], np.abs(p["elem_H"]), m, nc, rows)
         # Every entry is summed along a tree whose depth is bounded by the
-        # plan length of a fine block (< 64 here), the in-tile scan and carries
-        # (< 24) and the cross-tile fix-up (< 24 + tiles/256); so the error is
-        # at most gamma_D sum|terms| (plus one rounding of each term to float32).
-        depth = 112 + (d.mesh.fine_nnzb // (256 * 256) + 1)
+        # plan length of a fine block, the in-tile scan and carries (< 24)
+        # and the cross-tile fix-up (< 24 + tiles/256); so the error is at
+        # most gamma_D sum|terms| (plus one rounding of each term to float32).
+        depth = _max_plan(p) + 48 + (d.mesh.fine_nnzb // (256 * 256) + 1)
         u = gamma(depth) if dt == agc.AGC_F64 else gamma(depth, U32) + U32
         for r in rows:
             for k in range(rp[r], rp[r + 1]):
