@@ -201,8 +201,10 @@ typedef struct {
   int32_t max_refine;  /* mixed: cap on inner solves (the first one and its
                           refinement steps)                                   */
   int32_t timing;      /* 1: fill the ms_* phase times of agc_solve_info;
-                          2: also time every PCG SpMV launch with HIP events
-                          (spmv_launches, ms_spmv)                            */
+                          2: also, after each PCG solve, replay its SpMV
+                          kernel 20 times back to back between two HIP
+                          events (spmv_launches, ms_spmv; the replays add
+                          to ms_pcg)                                         */
 } agc_solve_opts;
 
 typedef struct {
@@ -213,7 +215,7 @@ typedef struct {
                           float64 residual b_c - A_c x_c (0 for FP64)        */
   double rel_res;      /* final float64 relative residual of the coarse system */
   float ms_aggregate, ms_assemble, ms_pcg, ms_prolong;  /* when timing >= 1   */
-  int32_t spmv_launches;  /* when timing = 2: PCG SpMV launches that did work  */
+  int32_t spmv_launches;  /* when timing = 2: timed SpMV replay launches        */
   float ms_spmv;          /* when timing = 2: their summed duration            */
 } agc_solve_info;
 

@@ -78,16 +78,43 @@ __global__ void k_cc_link_min(const int32_t* __restrict__ edges, const uint8_t* 
 // in the edge's component and the value only decreases, so the forest stays
 // valid; a pointer it replaces may drop a link, which the final lock-free
 // pass over every edge restores.
+// Lanes of a wave that hook the same vertex first take the minimum of their
+// targets, so each distinct vertex costs one atomic per wave (the trees of a
+// large component meet along long boundaries, whose edges sit side by side
+// in the edge list).  The loop bound is uniform per workgroup, so every lane
+// of a wave takes part in the lane exchanges.
 __global__ void k_cc_link_roots(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
                                 int32_t* parent, int32_t n) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-    const int2 uv = reinterpret_cast<const int2*>(edges)[e];
-    const int32_t u = uv.x, v = uv.y;
-    if (tags[e] != 1 || u == v || u < 0 || u >= n || v < 0 || v >= n) continue;
-    const int32_t pu = parent[u], pv = parent[v];
-    if (pu == pv) continue;
-    const int32_t lo = pu < pv ? pu : pv, hi = pu < pv ? pv : pu;
-    if (parent[hi] > lo) atomicMin(parent + hi, lo);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+    const int64_t e = base + threadIdx.x;
+    bool want = false;
+    int32_t lo = 0, hi = 0;
+    if (e < m && tags[e] == 1) {
+      const int2 uv = reinterpret_cast<const int2*>(edges)[e];
+      const int32_t u = uv.x, v = uv.y;
+      if (u != v && u >= 0 && u < n && v >= 0 && v < n) {
+        const int32_t pu = parent[u], pv = parent[v];
+        lo = pu < pv ? pu : pv;
+        hi = pu < pv ? pv : pu;
+        want = pu != pv && parent[hi] > lo;
+      }
+    }
+    uint64_t pend = __ballot(want);
+    while (pend) {
+      const int leader = __ffsll((unsigned long long)pend) - 1;
+      const int32_t h = __shfl(hi, leader);
+      const bool mine = want && hi == h;
+      int32_t mn = mine ? lo : INT32_MAX;
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) {
+        const int32_t o = __shfl_xor(mn, d);
+        mn = o < mn ? o : mn;
+      }
+      if ((int)lane_id() == leader) atomicMin(parent + h, mn);
+      pend &= ~__ballot(mine);
+      want = want && !mine;
+    }
   }
 }
 

@@ -209,7 +209,6 @@ agc_status agc_create(agc_context** out, int32_t device, void* stream) {
     AGC_HIP(hipMalloc(&c->d_pcg, sizeof(agc::PcgState)));
     AGC_HIP(hipHostMalloc(&c->h_pcg, sizeof(agc::PcgState), hipHostMallocDefault));
     for (auto& e : c->ev) AGC_HIP(hipEventCreate(&e));
-    for (auto& e : c->kev) AGC_HIP(hipEventCreate(&e));
   } catch (const Error& e) {
     agc_destroy(c);
     return e.code;
@@ -237,8 +236,6 @@ agc_status agc_destroy(agc_context* c) {
   if (c->d_pcg) (void)hipFree(c->d_pcg);
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   for (auto& e : c->ev)
-    if (e) (void)hipEventDestroy(e);
-  for (auto& e : c->kev)
     if (e) (void)hipEventDestroy(e);
   delete c;
   return AGC_OK;
@@ -466,6 +463,10 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   const int32_t n = mesh.n_verts;
   AGC_REQUIRE(o->coarsen == 0 || p->n_edges == 0 || (p->edges && p->tags), "edges/tags null");
   Timer tm(c, o->timing != 0);
+  struct KernelTiming {   // on for this call only, also when it throws
+    agc_context* c;
+    ~KernelTiming() { c->kernel_timing = false; }
+  } kt_scope{c};
   c->kernel_timing = o->timing >= 2;
   c->spmv_ms = 0.0;
   c->spmv_n = 0;
@@ -495,7 +496,6 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   }
   tm.mark();                                                   // 4
   AGC_HIP(hipStreamSynchronize(c->stream));
-  c->kernel_timing = false;
   if (info) {
     info->n_coarse = R.n_c;
     info->nnzb = res.nnzb;

@@ -150,10 +150,9 @@ struct agc_context {
   unsigned* h_err = nullptr;   // pinned host mirror
   void* d_pcg = nullptr;       // device PCG state (agc::PcgState)
   void* h_pcg = nullptr;       // pinned host mirror
-  hipEvent_t ev[8] = {};
-  hipEvent_t kev[2 * agc::kMaxChunk] = {};   // per-launch events for kernel timing
-  bool kernel_timing = false;
-  double spmv_ms = 0.0;                      // summed duration of timed SpMV launches
+  hipEvent_t ev[8] = {};        // 0-4 phase timer, 6-7 SpMV replay timing
+  bool kernel_timing = false;   // replay and time the PCG SpMV after each PCG solve
+  double spmv_ms = 0.0;         // summed duration of the timed SpMV launches
   int64_t spmv_n = 0;
   agc::Matrix solve_a;         // matrices reused across agc_solve calls
   agc::Matrix solve_a64;

@@ -325,13 +325,56 @@ def contact_problem(seed: int, n_bodies: int = 96, body=(4, 8, 24), n_contacts: 
     }
 
 
+def drift_fraction(p: dict, delta: float, sample=None) -> float:
+    """Fraction of edge tags that change when the field moves by delta along p's drift
+    direction (on the edge subset ``sample``, ranked within it, when given)."""
+    u = p["drift_dir"]
+    edges = p["edges"] if sample is None else p["edges"][sample]
+    t0 = edge_tags(p["field"], p["pos"], edges, p["frac"])
+    t1 = edge_tags(p["field"], p["pos"], edges, p["frac"], shift=delta * u)
+    return float(np.mean(t1 != t0))
+
+
+def calibrate_drift(p: dict, target: float = 0.10, iters: int = 16, max_sample: int = 1 << 20) -> float:
+    """Step length delta whose one-step tag flip fraction is about ``target`` (bisection on
+    the host over a seeded sample of at most max_sample edges)."""
+    m = p["edges"].shape[0]
+    sample = None
+    if m > max_sample:
+        sample = np.sort(rng_for(p["seed"], S_DRIFT).choice(m, size=max_sample, replace=False))
+    lo, hi = 0.0, 1.0
+    while drift_fraction(p, hi, sample) < target and hi < 64.0:
+        hi *= 2.0
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if drift_fraction(p, mid, sample) < target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def drift_tags(p: dict, it: int) -> np.ndarray:
+    """Tags of system ``it`` of a drifting sequence: the field advected by it * delta along the
+    seeded direction (a stand-in for the activity moving between Newton iterations)."""
+    shift = it * p["drift_delta"] * p["drift_dir"]
+    return edge_tags(p["field"], p["pos"], p["edges"], p["frac"], shift=shift)
+
+
+def with_drift(p: dict, target: float = 0.10) -> dict:
+    u = rng_for(p["seed"], S_DRIFT).standard_normal(3)
+    p["drift_dir"] = u / np.linalg.norm(u)
+    p["drift_delta"] = calibrate_drift(p, target)
+    return p
+
+
 # The measured workloads.
 CONFIGS = {
     "c1": dict(n=8, seed=1, frac=0.7),      # 729 vertices, 2560 tets, FP64, PCG rtol 1e-10
     "c2": dict(n=64, seed=2, frac=0.6),     # 274,625 vertices, 1.31M tets, FP64 and mixed
     "c3": dict(contact=True, seed=3),       # 96 bodies, 108,000 vertices, 368,640 tets + 250k contacts
     "c4": dict(n=32, seed=4, frac=0.7),     # 35,937 vertices, adjoint
-    "c5": dict(n=128, seed=5, frac=0.6),    # 2.15M vertices, re-aggregation
+    "c5": dict(n=128, seed=5, frac=0.6, drift=True),   # 2.15M vertices, 10 drifting systems
 }
 
 
@@ -341,6 +384,8 @@ def make_config(name: str) -> dict:
         p = contact_problem(c["seed"])
     else:
         p = grid_problem(c["n"], c["seed"], c["frac"])
+    if c.get("drift"):
+        with_drift(p)
     p["name"] = name
     return p
 
