@@ -89,6 +89,41 @@ agc_status agc_mesh_destroy(agc_context* ctx, agc_mesh* mesh);
 agc_status agc_mesh_info(const agc_mesh* mesh, int32_t* n_verts, int64_t* n_elems,
                          int64_t* fine_nnzb);
 
+/* ---------------------------------------------- edge tags (before the map) */
+
+/* Green-strain-increment criterion (Sec. 4.2 "Adaptive Coarsening
+ * Criterion", Eq. 3).  For each tetrahedron, F = Ds Dm^{-1} (columns of Ds /
+ * Dm: x_k - x_0 of the deformed / rest element, k = 1..3), G = (F^T F - I)/2,
+ * and dG = G(x_cur) - G(x_prev) between two successive Newton iterates.  An
+ * edge is tagged 0 (protected) when any tetrahedron containing it has
+ * ||dG||_F > threshold, else 1 (collapsible); an edge in no tetrahedron, or a
+ * self-loop, stays 1.
+ *
+ * The connectivity is static, so agc_tagger_create precomputes every
+ * tetrahedron's Dm^{-1} and the position of each of its six edges in the
+ * edge list; the tagger owns that device data until agc_tagger_destroy.
+ *   tets  : [n_tets][4] int32 device, distinct ids in [0, n_verts).
+ *   rest  : [n_verts][3] float64 device, rest positions.
+ *   edges : [n_edges][2] int32 device, 8-byte aligned, the list agc_aggregate
+ *           will receive (duplicates and self-loops allowed).
+ * AGC_ERR_BAD_INPUT for an id out of range, a repeated vertex in a
+ * tetrahedron or a rest tetrahedron of zero volume.  Synchronises. */
+typedef struct agc_tagger agc_tagger;
+agc_status agc_tagger_create(agc_context* ctx, int32_t n_verts, int64_t n_tets, const int32_t* tets,
+                             const double* rest, int64_t n_edges, const int32_t* edges,
+                             agc_tagger** out);
+agc_status agc_tagger_destroy(agc_context* ctx, agc_tagger* tagger);
+
+/* Tags for one Newton iteration.
+ *   x_cur, x_prev : [n_verts][3] float64 device, positions at iterates i, i-1.
+ *   threshold     : >= 0 (the paper uses 5e-5).
+ *   tags          : [n_edges] uint8 device out.
+ *   n_protected   : [host] out, number of tags 0; may be NULL (then the call
+ *                   does not synchronise). */
+agc_status agc_tag_edges(agc_context* ctx, const agc_tagger* tagger, const double* x_cur,
+                         const double* x_prev, double threshold, uint8_t* tags,
+                         int64_t* n_protected);
+
 /* -------------------------------------------------------------- (a) map */
 
 /* Fine-to-coarse aggregation (Sec. 4.1; supplement Sec. 1): super-nodes are
@@ -205,6 +240,10 @@ typedef struct {
                           kernel 20 times back to back between two HIP
                           events (spmv_launches, ms_spmv; the replays add
                           to ms_pcg)                                         */
+  int32_t post_iters;  /* post-coarsening (Sec. 4.3): with coarsen = 1, at
+                          most this many block-Jacobi PCG iterations on the
+                          fine system H x = g from the prolongated x, in
+                          float64, stopping early at rtol; 0 = off          */
 } agc_solve_opts;
 
 typedef struct {
@@ -217,6 +256,12 @@ typedef struct {
   float ms_aggregate, ms_assemble, ms_pcg, ms_prolong;  /* when timing >= 1   */
   int32_t spmv_launches;  /* when timing = 2: timed SpMV replay launches        */
   float ms_spmv;          /* when timing = 2: their summed duration            */
+  int32_t post_iters;     /* post-coarsening iterations performed              */
+  double fine_rel_res;    /* with post_iters > 0: ||g - H x||_2 / ||g||_2 of
+                             the fine system before (fine_rel_res0) and after
+                             post-coarsening, float64 matrix                  */
+  double fine_rel_res0;
+  float ms_post;          /* when timing >= 1: fine assembly + post PCG      */
 } agc_solve_info;
 
 /* One Newton linear solve, steps in the order of Alg. overview (mapping,
@@ -233,7 +278,8 @@ agc_status agc_solve(agc_context* ctx, const agc_problem* prob, const agc_solve_
  * Only the map (and x) from the forward pass are needed; A_c is assembled
  * again, never stored.  dg: [n_verts][3] float64 out; dH: [n_elems][144]
  * float64 out, may be NULL.  opts->precision selects the solve as in
- * agc_solve.  Synchronises. */
+ * agc_solve; opts->post_iters must be 0 (the derivative is that of the
+ * coarsened solve).  Synchronises. */
 agc_status agc_solve_backward(agc_context* ctx, const agc_problem* prob,
                               const agc_solve_opts* opts, const int32_t* map, int32_t n_coarse,
                               const double* x, const double* w, double* dg, double* dH,

@@ -31,7 +31,7 @@ EXPORTS = (
     "agc_mesh_create", "agc_mesh_destroy", "agc_mesh_info", "agc_aggregate",
     "agc_assemble_coarse", "agc_assemble_fine", "agc_matrix_destroy", "agc_matrix_info",
     "agc_matrix_copy", "agc_spmv", "agc_pcg", "agc_prolongate", "agc_restrict", "agc_solve",
-    "agc_solve_backward", "agc_time_spmv",
+    "agc_solve_backward", "agc_time_spmv", "agc_tagger_create", "agc_tagger_destroy", "agc_tag_edges",
 )
 
 
@@ -60,13 +60,14 @@ class agc_problem(ctypes.Structure):
 
 class agc_solve_opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("coarsen", c_int32), ("rtol", c_double), ("max_iter", c_int32),
-                ("inner_rtol", c_double), ("max_refine", c_int32), ("timing", c_int32)]
+                ("inner_rtol", c_double), ("max_refine", c_int32), ("timing", c_int32), ("post_iters", c_int32)]
 
 
 class agc_solve_info(ctypes.Structure):
     _fields_ = [("n_coarse", c_int32), ("nnzb", c_int64), ("pcg_iters", c_int32), ("refine_iters", c_int32),
                 ("rel_res", c_double), ("ms_aggregate", c_float), ("ms_assemble", c_float),
-                ("ms_pcg", c_float), ("ms_prolong", c_float), ("spmv_launches", c_int32), ("ms_spmv", c_float)]
+                ("ms_pcg", c_float), ("ms_prolong", c_float), ("spmv_launches", c_int32), ("ms_spmv", c_float),
+                ("post_iters", c_int32), ("fine_rel_res", c_double), ("fine_rel_res0", c_double), ("ms_post", c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +93,9 @@ def _load():
         "agc_mesh_destroy": (S, [P, P]),
         "agc_mesh_info": (S, [P, POINTER(c_int32), POINTER(c_int64), POINTER(c_int64)]),
         "agc_aggregate": (S, [P, c_int32, c_int64, P, P, P, POINTER(c_int32)]),
+        "agc_tagger_create": (S, [P, c_int32, c_int64, P, P, c_int64, P, POINTER(c_void_p)]),
+        "agc_tagger_destroy": (S, [P, P]),
+        "agc_tag_edges": (S, [P, P, P, P, c_double, P, POINTER(c_int64)]),
         "agc_assemble_coarse": (S, [P, P, P, c_int32, P, P, c_int32, c_int32, POINTER(c_void_p), P]),
         "agc_assemble_fine": (S, [P, P, P, c_int32, c_int32, POINTER(c_void_p)]),
         "agc_matrix_destroy": (S, [P, P]),
@@ -195,6 +199,24 @@ class Mesh:
             pass
 
 
+class Tagger:
+    """Static data of the Green-strain-increment criterion for a tet mesh and an edge list."""
+
+    def __init__(self, ctx: Context, h, n_verts, n_tets, n_edges):
+        self.ctx, self.h, self.n_verts, self.n_tets, self.n_edges = ctx, h, n_verts, n_tets, n_edges
+
+    def close(self):
+        if getattr(self, "h", None) and self.ctx.h:
+            _lib.agc_tagger_destroy(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Matrix:
     def __init__(self, ctx: Context, h):
         self.ctx, self.h = ctx, h
@@ -243,6 +265,31 @@ def agc_aggregate(ctx: Context, n_verts: int, edges: torch.Tensor, tags: torch.T
     nc = c_int32()
     _check(ctx.h, _lib.agc_aggregate(ctx.h, int(n_verts), int(m), _ptr(edges), _ptr(tags), _ptr(mp), byref(nc)))
     return mp, nc.value
+
+
+def agc_tagger_create(ctx: Context, n_verts: int, tets: torch.Tensor, rest: torch.Tensor,
+                      edges: torch.Tensor) -> Tagger:
+    ne, m = tets.shape[0], edges.shape[0]
+    _dev(tets, torch.int32, (ne, 4), "tets", ctx.device)
+    _dev(rest, torch.float64, (n_verts, 3), "rest", ctx.device)
+    _dev(edges, torch.int32, (m, 2), "edges", ctx.device)
+    h = c_void_p()
+    _check(ctx.h, _lib.agc_tagger_create(ctx.h, int(n_verts), int(ne), _ptr(tets), _ptr(rest), int(m),
+                                         _ptr(edges), byref(h)))
+    return Tagger(ctx, h, int(n_verts), int(ne), int(m))
+
+
+def agc_tag_edges(ctx: Context, tagger: Tagger, x_cur: torch.Tensor, x_prev: torch.Tensor, threshold: float,
+                  tags_out=None, count=True):
+    """(tags uint8 [n_edges] on the device, number protected or None)."""
+    _dev(x_cur, torch.float64, (tagger.n_verts, 3), "x_cur", ctx.device)
+    _dev(x_prev, torch.float64, (tagger.n_verts, 3), "x_prev", ctx.device)
+    tags = torch.empty(tagger.n_edges, dtype=torch.uint8, device=ctx.device) if tags_out is None else tags_out
+    _dev(tags, torch.uint8, (tagger.n_edges,), "tags", ctx.device)
+    n = c_int64()
+    _check(ctx.h, _lib.agc_tag_edges(ctx.h, tagger.h, _ptr(x_cur), _ptr(x_prev), float(threshold), _ptr(tags),
+                                     byref(n) if count else None))
+    return tags, (n.value if count else None)
 
 
 def _h_dtype(t):
@@ -323,9 +370,9 @@ def agc_restrict(ctx: Context, map_: torch.Tensor, n_coarse: int, v: torch.Tenso
 
 
 def make_opts(precision=AGC_PREC_FP64, coarsen=1, rtol=1e-10, max_iter=20000, inner_rtol=1e-4, max_refine=20,
-              timing=0) -> agc_solve_opts:
+              timing=0, post_iters=0) -> agc_solve_opts:
     return agc_solve_opts(int(precision), int(coarsen), float(rtol), int(max_iter), float(inner_rtol),
-                          int(max_refine), int(timing))
+                          int(max_refine), int(timing), int(post_iters))
 
 
 def make_problem(mesh: Mesh, edges, tags, elem_H, g) -> agc_problem:

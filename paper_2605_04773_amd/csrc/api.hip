@@ -17,27 +17,6 @@ namespace {
 
 using agc::Error;
 
-#define API_BEGIN(ctx)                                \
-  if (!(ctx)) return AGC_ERR_INVALID_ARG;             \
-  (ctx)->err.clear();                                 \
-  try {                                               \
-    AGC_HIP(hipSetDevice((ctx)->device));
-
-#define API_END(ctx)                                  \
-  }                                                   \
-  catch (const Error& e) {                            \
-    (ctx)->err = e.what();                            \
-    return e.code;                                    \
-  }                                                   \
-  catch (const std::exception& e) {                   \
-    (ctx)->err = e.what();                            \
-    return AGC_ERR_DEVICE;                            \
-  }                                                   \
-  catch (...) {                                       \
-    (ctx)->err = "unknown failure";                   \
-    return AGC_ERR_DEVICE;                            \
-  }                                                   \
-  return AGC_OK;
 
 __global__ void k_iota_i32(int32_t* __restrict__ v, int32_t n) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
@@ -87,6 +66,7 @@ void validate_opts(const agc_solve_opts* o) {
   AGC_REQUIRE(o->coarsen == 0 || o->coarsen == 1, "coarsen must be 0 or 1");
   AGC_REQUIRE(o->rtol > 0.0 && o->rtol < 1.0, "rtol must be in (0, 1)");
   AGC_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
+  AGC_REQUIRE(o->post_iters >= 0, "post_iters must be >= 0");
   if (o->precision == AGC_PREC_MIXED) {
     AGC_REQUIRE(o->inner_rtol > 0.0 && o->inner_rtol < 1.0, "inner_rtol must be in (0, 1)");
     AGC_REQUIRE(o->max_refine >= 1, "max_refine must be >= 1");
@@ -230,6 +210,7 @@ agc_status agc_destroy(agc_context* c) {
   else (void)hipDeviceSynchronize();
   c->solve_a.release();
   c->solve_a64.release();
+  c->solve_fine.release();
   c->ws.release();
   if (c->d_err) (void)hipFree(c->d_err);
   if (c->h_err) (void)hipHostFree(c->h_err);
@@ -495,6 +476,27 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
     agc::prolongate(c, n, R.map, R.n_c, x_c, x);
   }
   tm.mark();                                                   // 4
+  // post-coarsening (Sec. 4.3): a few fine PCG iterations from x = P x_c
+  int32_t post_done = 0;
+  double fine_rel0 = 0.0, fine_rel = 0.0;
+  if (o->post_iters > 0 && R.map) {
+    agc::Matrix& F = c->solve_fine;
+    agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, F);
+    const int64_t n3 = 3 * (int64_t)n;
+    double* y = c->ws.get<double>("post.y", n3);
+    double* r = c->ws.get<double>("post.r", n3);
+    double gn = 0.0;
+    agc::spmv(c, F, x, y);
+    agc::residual_norms(c, p->g, y, r, n3, &gn, &fine_rel0);
+    fine_rel0 = gn > 0.0 ? fine_rel0 / gn : 0.0;
+    double rel = 0.0;
+    const int st = agc::pcg(c, F, p->g, x, o->rtol, o->post_iters, &post_done, &rel);
+    if (st != AGC_OK && st != AGC_ERR_NOT_CONVERGED) check_status(st, "post-coarsening PCG");
+    agc::spmv(c, F, x, y);
+    agc::residual_norms(c, p->g, y, r, n3, &gn, &fine_rel);
+    fine_rel = gn > 0.0 ? fine_rel / gn : 0.0;
+  }
+  tm.mark();                                                   // 5
   AGC_HIP(hipStreamSynchronize(c->stream));
   if (info) {
     info->n_coarse = R.n_c;
@@ -508,6 +510,10 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
     info->ms_prolong = tm.ms(3, 4);
     info->spmv_launches = (int32_t)c->spmv_n;
     info->ms_spmv = (float)c->spmv_ms;
+    info->post_iters = post_done;
+    info->fine_rel_res = fine_rel;
+    info->fine_rel_res0 = fine_rel0;
+    info->ms_post = tm.ms(4, 5);
   }
   API_END(c)
 }
@@ -518,6 +524,7 @@ agc_status agc_solve_backward(agc_context* c, const agc_problem* p, const agc_so
   API_BEGIN(c)
   validate_problem(p);
   validate_opts(o);
+  AGC_REQUIRE(o->post_iters == 0, "post_iters must be 0 for the derivative of the coarsened solve");
   AGC_REQUIRE(x && w && dg, "null pointer");
   const agc::Mesh& mesh = p->mesh->m;
   const int32_t n = mesh.n_verts;

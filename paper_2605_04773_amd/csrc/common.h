@@ -90,7 +90,13 @@ class Workspace {
 
 // Bits of the per-call device error word.
 enum : unsigned { kErrRange = 1u, kErrTag = 2u, kErrElem = 4u, kErrMap = 8u, kErrNoDiag = 16u,
-                  kErrNotSPD = 32u };
+                  kErrNotSPD = 32u, kErrDegenerate = 64u };
+
+inline unsigned grid_blocks(int64_t n) {   // grid for a grid-stride loop over n items
+  int64_t b = (n + kWG - 1) / kWG;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b < 1 ? 1 : b);
+}
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 

@@ -150,10 +150,35 @@ struct agc_context {
   unsigned* h_err = nullptr;   // pinned host mirror
   void* d_pcg = nullptr;       // device PCG state (agc::PcgState)
   void* h_pcg = nullptr;       // pinned host mirror
-  hipEvent_t ev[8] = {};        // 0-4 phase timer, 6-7 SpMV replay timing
+  hipEvent_t ev[8] = {};        // 0-5 phase timer, 6-7 SpMV replay timing
   bool kernel_timing = false;   // replay and time the PCG SpMV after each PCG solve
   double spmv_ms = 0.0;         // summed duration of the timed SpMV launches
   int64_t spmv_n = 0;
   agc::Matrix solve_a;         // matrices reused across agc_solve calls
   agc::Matrix solve_a64;
+  agc::Matrix solve_fine;      // the fine system for post-coarsening
 };
+
+// Entry-point frame: a C++ exception never crosses the ABI; its message is
+// kept in the context and its code returned.
+#define API_BEGIN(ctx)                                \
+  if (!(ctx)) return AGC_ERR_INVALID_ARG;             \
+  (ctx)->err.clear();                                 \
+  try {                                               \
+    AGC_HIP(hipSetDevice((ctx)->device));
+
+#define API_END(ctx)                                  \
+  }                                                   \
+  catch (const ::agc::Error& e) {                     \
+    (ctx)->err = e.what();                            \
+    return e.code;                                    \
+  }                                                   \
+  catch (const std::exception& e) {                   \
+    (ctx)->err = e.what();                            \
+    return AGC_ERR_DEVICE;                            \
+  }                                                   \
+  catch (...) {                                       \
+    (ctx)->err = "unknown failure";                   \
+    return AGC_ERR_DEVICE;                            \
+  }                                                   \
+  return AGC_OK;

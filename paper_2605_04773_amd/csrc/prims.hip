@@ -240,6 +240,7 @@ void err_throw(unsigned bits) {
   if (bits & kErrElem) m += " element with a repeated or out-of-range vertex;";
   if (bits & kErrMap) m += " map value out of range;";
   if (bits & kErrNoDiag) m += " row without a diagonal block;";
+  if (bits & kErrDegenerate) m += " rest element with zero volume;";
   int code = AGC_ERR_BAD_INPUT;
   if (bits & kErrNotSPD) {
     m += " diagonal 3x3 block not positive definite;";

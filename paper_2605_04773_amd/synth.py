@@ -22,7 +22,7 @@ when the mean of the field at its two endpoints ranks among the lowest
 
 Random streams: ``np.random.default_rng(SeedSequence([seed, stream]))`` with
 stream 0 rotations, 1 field, 2 gradient, 3 adjoint seed w, 4 finite-difference
-directions, 5 jitter, 6 contact, 7 drift.
+directions, 5 jitter, 6 contact, 7 drift, 8 deformation states.
 """
 from __future__ import annotations
 
@@ -35,7 +35,7 @@ POISSON = 0.4
 DENSITY = 1000.0
 H_STEP = 1.0e-2
 
-S_ROT, S_FIELD, S_GRAD, S_W, S_FD, S_JITTER, S_CONTACT, S_DRIFT = range(8)
+S_ROT, S_FIELD, S_GRAD, S_W, S_FD, S_JITTER, S_CONTACT, S_DRIFT, S_STATES = range(9)
 
 
 def rng_for(seed: int, stream: int) -> np.random.Generator:
@@ -366,6 +366,49 @@ def with_drift(p: dict, target: float = 0.10) -> dict:
     p["drift_dir"] = u / np.linalg.norm(u)
     p["drift_delta"] = calibrate_drift(p, target)
     return p
+
+
+def deformation_states(p: dict, wave_amp: float = 2e-4, wave_cycles: float = 3.0, width: float = 0.15,
+                       background: float = 1e-6) -> tuple[np.ndarray, np.ndarray]:
+    """Positions at two successive Newton iterates (previous, current) of the mesh of p.
+
+    Both are rigid motions (a random rotation about the body's centre plus a
+    translation, different for the two states) of the rest shape plus a
+    displacement field: a smooth background of amplitude ``background`` at
+    one cycle per unit length, changing between the two states, and in the
+    current state an elastic wave packet of amplitude ``wave_amp`` with
+    ``wave_cycles`` cycles per unit length under a Gaussian envelope of width
+    ``width`` around a random point.  The Green strain increment is then
+    large inside the packet and small elsewhere (rigid motions leave G
+    unchanged).
+    """
+    rng = rng_for(p["seed"], S_STATES)
+    rest = p["pos"]
+    c = rest.mean(axis=0)
+    lo, hi = rest.min(axis=0), rest.max(axis=0)
+
+    def smooth(k_dir, phase):
+        arg = 2.0 * math.pi * (rest @ k_dir) + phase
+        return np.sin(arg)[:, None] * rng.standard_normal(3)[None, :]
+
+    def rigid(x):
+        r = random_rotations(rng, 1)[0]
+        return (x - c) @ r.T + c + rng.uniform(-0.1, 0.1, size=3)
+
+    d1 = rng.standard_normal(3)
+    d1 /= np.linalg.norm(d1)
+    d2 = rng.standard_normal(3)
+    d2 /= np.linalg.norm(d2)
+    u_prev = background * smooth(d1, rng.uniform(0, 2 * math.pi))
+    u_cur = background * smooth(d2, rng.uniform(0, 2 * math.pi))
+    centre = lo + rng.uniform(0.25, 0.75, size=3) * (hi - lo)
+    kw = rng.standard_normal(3)
+    kw *= wave_cycles / np.linalg.norm(kw)
+    env = np.exp(-np.sum((rest - centre) ** 2, axis=1) / (width * width))
+    pol = rng.standard_normal(3)
+    pol /= np.linalg.norm(pol)
+    u_cur = u_cur + wave_amp * (env * np.sin(2.0 * math.pi * (rest @ kw)))[:, None] * pol[None, :]
+    return rigid(rest + u_prev), rigid(rest + u_cur)
 
 
 # The measured workloads.

@@ -233,3 +233,37 @@ def test_full_size(ctx, name, mode):
     err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
     log(f"   rtol {rtol:g}: iters={info.pcg_iters} refine={info.refine_iters} rel_res={info.rel_res:.2e} err={err:.2e}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["c1", "c4"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_post_coarsening_matches_oracle(ctx, name, precision):
+    """Post-coarsening (Sec. 4.3): k fine PCG iterations from the prolongated x.
+    The oracle's textbook PCG run from the GPU's own x = P x_c gives the same x
+    (1e-9 relative; both in float64), and the reported fine residuals are the
+    oracle's."""
+    from oracle import method as omet
+    agc = binding()
+    d = dev(ctx, name)
+    p = d.p
+    prec = agc.AGC_PREC_MIXED if precision == "mixed" else agc.AGC_PREC_FP64
+    log(f"[post] {name} {precision}")
+    x0, _, _ = run_solve(ctx, d, precision=prec, rtol=1e-9)
+    k = 10
+    x, _, info = run_solve(ctx, d, precision=prec, rtol=1e-9, post_iters=k)
+    assert info.post_iters == k
+    ref, its = omet.post_coarsen(p, x0, k)
+    assert its == k
+    err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    h = ogal.fine_hessian(p["n_verts"], p["elem_verts"], p["elem_H"])
+    g = p["g"].reshape(-1)
+    r0 = np.linalg.norm(g - h @ x0.reshape(-1)) / np.linalg.norm(g)
+    r1 = np.linalg.norm(g - h @ x.reshape(-1)) / np.linalg.norm(g)
+    log(f"   fine residual {info.fine_rel_res0:.3e} -> {info.fine_rel_res:.3e} (oracle {r0:.3e} -> {r1:.3e}); "
+        f"x vs oracle {err:.2e}")
+    assert err <= 1e-9
+    assert abs(info.fine_rel_res0 - r0) <= 1e-9 * r0 and abs(info.fine_rel_res - r1) <= 1e-6 * r1
+    assert r1 < r0
+    # the derivative is that of the coarsened solve only
+    with pytest.raises(agc.AgcError):
+        agc.agc_solve_backward(ctx, d.problem(), agc.make_opts(post_iters=2), None, 0, None, None, None, None)

@@ -321,3 +321,37 @@ def test_adjoint_all_collapsible_closed_form(c1):
     x, dg, dh = adjoint.adjoint(c1["n_verts"], c1["elem_verts"], c1["elem_H"], c1["g"], m, n_c, w, dense=True)
     expect = w.sum(axis=0) * c1["h"] ** 2 / synth.DENSITY
     assert np.allclose(dg, expect[None, :], rtol=1e-9, atol=0)
+
+
+# ------------------------------------------------------- post-coarsening
+
+def test_post_coarsen_is_cg_on_the_fine_system():
+    """Pins of post_coarsen from what CG guarantees, not from its own loop:
+    k = 0 returns x0; the H-norm error to the fine solution never grows; from
+    the fine solution nothing moves; enough iterations reach the fine solution."""
+    import scipy.sparse.linalg as spla
+    from oracle import galerkin as _gal
+    from oracle import method as _m
+    p = synth.make_config("c1")
+    co = _m.coarsened_solve(p, solver="sparse")
+    h = _gal.fine_hessian(p["n_verts"], p["elem_verts"], p["elem_H"])
+    x_star = spla.spsolve(h.tocsc(), p["g"].reshape(-1)).reshape(-1, 3)
+    x0 = co["x"]
+    x, its = _m.post_coarsen(p, x0, 0)
+    assert its == 0 and np.array_equal(x, x0)
+
+    def enorm(v):
+        d = (v - x_star).reshape(-1)
+        return float(np.sqrt(d @ (h @ d)))
+    prev = enorm(x0)
+    for k in (1, 2, 5, 10):
+        x, its = _m.post_coarsen(p, x0, k)
+        assert its == k
+        e = enorm(x)
+        assert e <= prev * (1 + 1e-12)
+        prev = e
+    assert prev < 0.5 * enorm(x0)                     # ten iterations do reduce the error
+    x, _ = _m.post_coarsen(p, x_star, 3, rtol=1e-12)
+    assert np.linalg.norm(x - x_star) <= 1e-9 * np.linalg.norm(x_star)
+    x, its = _m.post_coarsen(p, x0, 2000, rtol=1e-13)
+    assert np.linalg.norm(x - x_star) <= 1e-8 * np.linalg.norm(x_star)
