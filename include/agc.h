@@ -166,6 +166,27 @@ agc_status agc_assemble_coarse(agc_context* ctx, const agc_mesh* mesh,
                                const double* g, const int32_t* map, int32_t n_coarse,
                                int32_t out_dtype, agc_matrix** A_c, double* g_c);
 
+/* The coarse system with adaptive affine embedding (Sec. 4.2 "Adaptive
+ * Affine Embedding", Eq. 4; supplement Sec. 2, Alg. 3-4): a coarse node
+ * whose aggregate has more than `threshold` members carries 12 DoF,
+ * x_f = sum_k Xbar_f[k] q_c[k] over four 3-blocks k with Xbar_f = (X, Y, Z, 1)
+ * the homogeneous rest coordinate of member f in its aggregate's frame
+ * (origin at the aggregate's smallest-id member: the same affine span as
+ * global coordinates, with the four 3-blocks on comparable scales); every
+ * other node keeps 3.
+ * Nodes are reordered with the 3-DoF ones first (each group in canonical
+ * label order); a 12-DoF node's four 3-blocks follow consecutively, so A_c
+ * is a 3x3-block matrix of n3 + 4 n12 block rows (sums in float64).
+ *   rest     : [n_verts][3] float64 rest positions.
+ *   g        : [n_verts][3] float64, may be NULL.
+ *   A_c      : [host] out, as for agc_assemble_coarse.
+ *   g_c      : [n3 + 4 n12][3] float64 out, may be NULL.
+ *   n3, n12  : [host] out, the node counts of each kind.  Synchronises. */
+agc_status agc_assemble_coarse_affine(agc_context* ctx, const agc_mesh* mesh, const double* elem_H,
+                                      const double* rest, const double* g, const int32_t* map,
+                                      int32_t n_coarse, int32_t threshold, agc_matrix** A_c,
+                                      double* g_c, int32_t* n3, int32_t* n12);
+
 /* The fine matrix H itself (map = identity), the comparator of the method.
  * It shares the mesh's static block pattern: destroy it before the mesh. */
 agc_status agc_assemble_fine(agc_context* ctx, const agc_mesh* mesh,
@@ -222,6 +243,8 @@ typedef struct {
   const double* elem_H;    /* [n_elems][144] float64 element blocks, 16-byte
                               aligned (AGC_ERR_INVALID_ARG otherwise)         */
   const double* g;         /* [n_verts][3] float64 gradient                    */
+  const double* rest;      /* [n_verts][3] float64 rest positions; needed only
+                              with opts.affine_threshold > 0                  */
 } agc_problem;
 
 typedef struct {
@@ -244,6 +267,10 @@ typedef struct {
                           most this many block-Jacobi PCG iterations on the
                           fine system H x = g from the prolongated x, in
                           float64, stopping early at rtol; 0 = off          */
+  int32_t affine_threshold; /* > 0: aggregates with more members than this
+                          get 12 DoF (adaptive affine embedding, as in
+                          agc_assemble_coarse_affine; the paper uses 32);
+                          0 = 3 DoF everywhere                               */
 } agc_solve_opts;
 
 typedef struct {
@@ -262,6 +289,9 @@ typedef struct {
                              post-coarsening, float64 matrix                  */
   double fine_rel_res0;
   float ms_post;          /* when timing >= 1: fine assembly + post PCG      */
+  int32_t n_affine;       /* coarse nodes with 12 DoF                          */
+  int32_t n_blocks;       /* 3x3 block rows of the coarse system: n_coarse
+                             + 3 n_affine                                     */
 } agc_solve_info;
 
 /* One Newton linear solve, steps in the order of Alg. overview (mapping,
@@ -278,8 +308,8 @@ agc_status agc_solve(agc_context* ctx, const agc_problem* prob, const agc_solve_
  * Only the map (and x) from the forward pass are needed; A_c is assembled
  * again, never stored.  dg: [n_verts][3] float64 out; dH: [n_elems][144]
  * float64 out, may be NULL.  opts->precision selects the solve as in
- * agc_solve; opts->post_iters must be 0 (the derivative is that of the
- * coarsened solve).  Synchronises. */
+ * agc_solve; opts->post_iters and opts->affine_threshold must be 0 (the
+ * derivative is that of the 3-DoF coarsened solve).  Synchronises. */
 agc_status agc_solve_backward(agc_context* ctx, const agc_problem* prob,
                               const agc_solve_opts* opts, const int32_t* map, int32_t n_coarse,
                               const double* x, const double* w, double* dg, double* dH,

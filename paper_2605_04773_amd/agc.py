@@ -32,6 +32,7 @@ EXPORTS = (
     "agc_assemble_coarse", "agc_assemble_fine", "agc_matrix_destroy", "agc_matrix_info",
     "agc_matrix_copy", "agc_spmv", "agc_pcg", "agc_prolongate", "agc_restrict", "agc_solve",
     "agc_solve_backward", "agc_time_spmv", "agc_tagger_create", "agc_tagger_destroy", "agc_tag_edges",
+    "agc_assemble_coarse_affine",
 )
 
 
@@ -55,19 +56,21 @@ class BadInput(AgcError):
 
 class agc_problem(ctypes.Structure):
     _fields_ = [("mesh", c_void_p), ("n_edges", c_int64), ("edges", c_void_p), ("tags", c_void_p),
-                ("elem_H", c_void_p), ("g", c_void_p)]
+                ("elem_H", c_void_p), ("g", c_void_p), ("rest", c_void_p)]
 
 
 class agc_solve_opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("coarsen", c_int32), ("rtol", c_double), ("max_iter", c_int32),
-                ("inner_rtol", c_double), ("max_refine", c_int32), ("timing", c_int32), ("post_iters", c_int32)]
+                ("inner_rtol", c_double), ("max_refine", c_int32), ("timing", c_int32), ("post_iters", c_int32),
+                ("affine_threshold", c_int32)]
 
 
 class agc_solve_info(ctypes.Structure):
     _fields_ = [("n_coarse", c_int32), ("nnzb", c_int64), ("pcg_iters", c_int32), ("refine_iters", c_int32),
                 ("rel_res", c_double), ("ms_aggregate", c_float), ("ms_assemble", c_float),
                 ("ms_pcg", c_float), ("ms_prolong", c_float), ("spmv_launches", c_int32), ("ms_spmv", c_float),
-                ("post_iters", c_int32), ("fine_rel_res", c_double), ("fine_rel_res0", c_double), ("ms_post", c_float)]
+                ("post_iters", c_int32), ("fine_rel_res", c_double), ("fine_rel_res0", c_double), ("ms_post", c_float),
+                ("n_affine", c_int32), ("n_blocks", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -95,6 +98,8 @@ def _load():
         "agc_aggregate": (S, [P, c_int32, c_int64, P, P, P, POINTER(c_int32)]),
         "agc_tagger_create": (S, [P, c_int32, c_int64, P, P, c_int64, P, POINTER(c_void_p)]),
         "agc_tagger_destroy": (S, [P, P]),
+        "agc_assemble_coarse_affine": (S, [P, P, P, P, P, P, c_int32, c_int32, POINTER(c_void_p), P,
+                                           POINTER(c_int32), POINTER(c_int32)]),
         "agc_tag_edges": (S, [P, P, P, P, c_double, P, POINTER(c_int64)]),
         "agc_assemble_coarse": (S, [P, P, P, c_int32, P, P, c_int32, c_int32, POINTER(c_void_p), P]),
         "agc_assemble_fine": (S, [P, P, P, c_int32, c_int32, POINTER(c_void_p)]),
@@ -267,6 +272,25 @@ def agc_aggregate(ctx: Context, n_verts: int, edges: torch.Tensor, tags: torch.T
     return mp, nc.value
 
 
+def agc_assemble_coarse_affine(ctx: Context, mesh: Mesh, elem_H: torch.Tensor, rest: torch.Tensor, g,
+                               map_: torch.Tensor, n_coarse: int, threshold: int):
+    """(A_c, g_c [n3 + 4 n12, 3] or None, n3, n12): the affine-embedded coarse system (float64)."""
+    _dev(elem_H, torch.float64, (mesh.n_elems, 144), "elem_H", ctx.device)
+    _dev(rest, torch.float64, (mesh.n_verts, 3), "rest", ctx.device)
+    _dev(map_, torch.int32, (mesh.n_verts,), "map", ctx.device)
+    if g is not None:
+        _dev(g, torch.float64, (mesh.n_verts, 3), "g", ctx.device)
+    # g_c needs n3 + 4 n12 rows, known only after the call: a bound of 4 n_coarse rows
+    g_c = torch.empty((4 * int(n_coarse), 3), dtype=torch.float64, device=ctx.device) if g is not None else None
+    h = c_void_p()
+    n3, n12 = c_int32(), c_int32()
+    _check(ctx.h, _lib.agc_assemble_coarse_affine(ctx.h, mesh.h, _ptr(elem_H), _ptr(rest), _ptr(g), _ptr(map_),
+                                                  int(n_coarse), int(threshold), byref(h), _ptr(g_c),
+                                                  byref(n3), byref(n12)))
+    nb = n3.value + 4 * n12.value
+    return Matrix(ctx, h), (g_c[:nb] if g_c is not None else None), n3.value, n12.value
+
+
 def agc_tagger_create(ctx: Context, n_verts: int, tets: torch.Tensor, rest: torch.Tensor,
                       edges: torch.Tensor) -> Tagger:
     ne, m = tets.shape[0], edges.shape[0]
@@ -370,12 +394,12 @@ def agc_restrict(ctx: Context, map_: torch.Tensor, n_coarse: int, v: torch.Tenso
 
 
 def make_opts(precision=AGC_PREC_FP64, coarsen=1, rtol=1e-10, max_iter=20000, inner_rtol=1e-4, max_refine=20,
-              timing=0, post_iters=0) -> agc_solve_opts:
+              timing=0, post_iters=0, affine_threshold=0) -> agc_solve_opts:
     return agc_solve_opts(int(precision), int(coarsen), float(rtol), int(max_iter), float(inner_rtol),
-                          int(max_refine), int(timing), int(post_iters))
+                          int(max_refine), int(timing), int(post_iters), int(affine_threshold))
 
 
-def make_problem(mesh: Mesh, edges, tags, elem_H, g) -> agc_problem:
+def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None) -> agc_problem:
     ctx = mesh.ctx
     m = 0 if edges is None else edges.shape[0]
     if edges is not None:
@@ -383,7 +407,9 @@ def make_problem(mesh: Mesh, edges, tags, elem_H, g) -> agc_problem:
         _dev(tags, torch.uint8, (m,), "tags", ctx.device)
     _dev(elem_H, torch.float64, (mesh.n_elems, 144), "elem_H", ctx.device)
     _dev(g, torch.float64, (mesh.n_verts, 3), "g", ctx.device)
-    return agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g))
+    if rest is not None:
+        _dev(rest, torch.float64, (mesh.n_verts, 3), "rest", ctx.device)
+    return agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g), _ptr(rest))
 
 
 def agc_solve(ctx: Context, prob: agc_problem, opts: agc_solve_opts, x: torch.Tensor, map_out=None):

@@ -279,4 +279,172 @@ void prolongate(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, cons
   AGC_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------- affine embedding
+
+__global__ void k_aff_init(uint32_t* __restrict__ cnt, int32_t* __restrict__ rep, int32_t n_c) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_c; c += (int64_t)gridDim.x * blockDim.x) {
+    cnt[c] = 0;
+    rep[c] = INT32_MAX;
+  }
+}
+
+// members per node and the smallest member (integer atomics: the result does
+// not depend on their order)
+__global__ void k_aff_count(const int32_t* __restrict__ map, int32_t n, int32_t n_c, uint32_t* __restrict__ cnt,
+                            int32_t* __restrict__ rep, unsigned* err) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = map[v];
+    if (c < 0 || c >= n_c) {
+      atomicOr(err, kErrMap);
+      continue;
+    }
+    atomicAdd(cnt + c, 1u);
+    atomicMin(rep + c, (int32_t)v);
+  }
+}
+
+// homogeneous rest coordinate of vertex v in the frame of its node c
+__device__ __forceinline__ double aff_coord(const double* __restrict__ rest, const int32_t* __restrict__ rep,
+                                            int64_t v, int32_t c, int q) {
+  return q < 3 ? rest[3 * v + q] - rest[3 * (int64_t)rep[c] + q] : 1.0;
+}
+
+// flag12[c] = (members > threshold); flag3[c] = the complement
+__global__ void k_aff_flags(const uint32_t* __restrict__ cnt, int32_t n_c, int32_t threshold,
+                            uint32_t* __restrict__ f3, uint32_t* __restrict__ f12) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_c; c += (int64_t)gridDim.x * blockDim.x) {
+    const bool big = cnt[c] > (uint32_t)threshold;
+    f3[c] = big ? 0u : 1u;
+    f12[c] = big ? 1u : 0u;
+  }
+}
+
+__global__ void k_aff_labels(const uint32_t* __restrict__ r3, const uint32_t* __restrict__ r12,
+                             const uint32_t* __restrict__ f12, int32_t n_c, int32_t* __restrict__ newlab,
+                             int32_t* __restrict__ offset) {
+  const int32_t n3 = (int32_t)r3[n_c];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_c; c += (int64_t)gridDim.x * blockDim.x) {
+    if (f12[c]) {
+      newlab[c] = n3 + (int32_t)r12[c];
+      offset[c] = n3 + 4 * (int32_t)r12[c];
+    } else {
+      newlab[c] = (int32_t)r3[c];
+      offset[c] = (int32_t)r3[c];
+    }
+  }
+}
+
+void affine_classify(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, int32_t threshold,
+                     const double* rest, AffineMap& am) {
+  AGC_REQUIRE(threshold >= 0, "affine threshold < 0");
+  AGC_REQUIRE(rest, "rest positions are required for the affine embedding");
+  am.n_c = n_c;
+  am.map = map;
+  am.rest = rest;
+  am.newlab = c->ws.get<int32_t>("aff.newlab", n_c);
+  am.offset = c->ws.get<int32_t>("aff.offset", n_c);
+  am.rep = c->ws.get<int32_t>("aff.rep", n_c);
+  uint32_t* cnt = c->ws.get<uint32_t>("aff.cnt", n_c);
+  uint32_t* f3 = c->ws.get<uint32_t>("aff.f3", n_c + 1);
+  uint32_t* f12 = c->ws.get<uint32_t>("aff.f12", n_c + 1);
+  uint32_t* r3 = c->ws.get<uint32_t>("aff.r3", n_c + 1);
+  uint32_t* r12 = c->ws.get<uint32_t>("aff.r12", n_c + 1);
+  err_reset(c);
+  k_aff_init<<<gs_blocks(n_c), kWG, 0, c->stream>>>(cnt, am.rep, n_c);
+  k_aff_count<<<gs_blocks(n), kWG, 0, c->stream>>>(map, n, n_c, cnt, am.rep, c->d_err);
+  k_aff_flags<<<gs_blocks(n_c), kWG, 0, c->stream>>>(cnt, n_c, threshold, f3, f12);
+  AGC_LAUNCH_CHECK();
+  scan_u32(c, f3, r3, n_c, "aff.s3");
+  scan_u32(c, f12, r12, n_c, "aff.s12");
+  k_aff_labels<<<gs_blocks(n_c), kWG, 0, c->stream>>>(r3, r12, f12, n_c, am.newlab, am.offset);
+  AGC_LAUNCH_CHECK();
+  uint32_t tot[2] = {0, 0};
+  AGC_HIP(hipMemcpyAsync(&tot[0], r3 + n_c, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  AGC_HIP(hipMemcpyAsync(&tot[1], r12 + n_c, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  err_throw(err_fetch(c));   // synchronises
+  am.n3 = (int32_t)tot[0];
+  am.n12 = (int32_t)tot[1];
+  const int64_t flat = (int64_t)am.n3 + 4 * (int64_t)am.n12;
+  AGC_REQUIRE(flat < INT32_MAX / 3, "too many coarse DoF");
+  am.n_flat = (int32_t)flat;
+}
+
+// Per member f of a node: its value weighted by the four homogeneous rest
+// coordinates (12 values); a 12-DoF node keeps all four sums, a 3-DoF node
+// the last (the plain sum).
+struct AffineRestrictOp {
+  const uint32_t* members;
+  const uint32_t* mkeys;
+  const double* v;
+  const double* rest;
+  const int32_t* rep;
+  const int32_t* newlab;
+  const int32_t* offset;
+  int32_t n3;
+  double* out;
+  __device__ void load(int64_t k, double x[12]) const {
+    const int64_t f = members[k];
+    const int32_t c = (int32_t)mkeys[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double w = aff_coord(rest, rep, f, c, q);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) x[3 * q + i] = w * v[3 * f + i];
+    }
+  }
+  __device__ void put(int64_t s, const double x[12], bool add) const {
+    const int64_t o = offset[s];
+    if (newlab[s] >= n3) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) out[3 * o + q] = add ? out[3 * o + q] + x[q] : x[q];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) out[3 * o + i] = add ? out[3 * o + i] + x[9 + i] : x[9 + i];
+    }
+  }
+  __device__ void store(int64_t s, const double x[12]) const { put(s, x, false); }
+  __device__ void add(int64_t s, const double x[12]) const { put(s, x, true); }
+};
+
+void affine_restrict(agc_context* c, int32_t n, const AffineMap& am, const uint32_t* members, const uint32_t* mkeys,
+                     const double* v, double* v_flat) {
+  AffineRestrictOp op{members, mkeys, v, am.rest, am.rep, am.newlab, am.offset, am.n3, v_flat};
+  seg_reduce<12, double, uint32_t, AffineRestrictOp>(c, mkeys, n, op, (uint32_t*)nullptr, false, "arst.seg");
+}
+
+__global__ void k_aff_prolong(const int32_t* __restrict__ map, int32_t n, int32_t n_c,
+                              const int32_t* __restrict__ newlab, const int32_t* __restrict__ offset, int32_t n3,
+                              const double* __restrict__ rest, const int32_t* __restrict__ rep,
+                              const double* __restrict__ xf,
+                              double* __restrict__ x, unsigned* err) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = map[v];
+    double o[3] = {0.0, 0.0, 0.0};
+    if (c < 0 || c >= n_c) {
+      atomicOr(err, kErrMap);
+    } else {
+      const int64_t b = offset[c];
+      if (newlab[c] >= n3) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double w = aff_coord(rest, rep, v, c, q);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) o[i] += w * xf[3 * (b + q) + i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) o[i] = xf[3 * b + i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x[3 * v + i] = o[i];
+  }
+}
+
+void affine_prolongate(agc_context* c, int32_t n, const AffineMap& am, const double* x_flat, double* x) {
+  k_aff_prolong<<<gs_blocks(n), kWG, 0, c->stream>>>(am.map, n, am.n_c, am.newlab, am.offset, am.n3, am.rest,
+                                                     am.rep, x_flat, x, c->d_err);
+  AGC_LAUNCH_CHECK();
+}
+
 }  // namespace agc

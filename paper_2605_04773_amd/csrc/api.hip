@@ -67,6 +67,7 @@ void validate_opts(const agc_solve_opts* o) {
   AGC_REQUIRE(o->rtol > 0.0 && o->rtol < 1.0, "rtol must be in (0, 1)");
   AGC_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
   AGC_REQUIRE(o->post_iters >= 0, "post_iters must be >= 0");
+  AGC_REQUIRE(o->affine_threshold >= 0, "affine_threshold must be >= 0");
   if (o->precision == AGC_PREC_MIXED) {
     AGC_REQUIRE(o->inner_rtol > 0.0 && o->inner_rtol < 1.0, "inner_rtol must be in (0, 1)");
     AGC_REQUIRE(o->max_refine >= 1, "max_refine must be >= 1");
@@ -90,9 +91,13 @@ struct Restrictor {
   const int32_t* map;        // nullptr: identity
   const uint32_t* members;
   const uint32_t* mkeys;
+  const agc::AffineMap* am = nullptr;   // set: affine embedding of the large aggregates
+  // coarse 3x3 block rows
+  int32_t blocks() const { return am ? am->n_flat : n_c; }
   // out = P^T v
   void apply(const double* v, double* out) const {
-    if (map) agc::restrict_sorted(c, n, n_c, members, mkeys, v, out);
+    if (am) agc::affine_restrict(c, n, *am, members, mkeys, v, out);
+    else if (map) agc::restrict_sorted(c, n, n_c, members, mkeys, v, out);
     else AGC_HIP(hipMemcpyAsync(out, v, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
   }
 };
@@ -107,8 +112,7 @@ struct SolveResult {
 SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_opts* o, const Restrictor& R,
                          const double* rhs_fine, double* x_c, Timer* tm) {
   const agc::Mesh& mesh = p->mesh->m;
-  const int32_t n_c = R.n_c;
-  const int64_t n3c = 3 * (int64_t)n_c;
+  const int64_t n3c = 3 * (int64_t)R.blocks();
   SolveResult res;
   double* b_c = c->ws.get<double>("solve.b", n3c);
   R.apply(rhs_fine, b_c);
@@ -118,7 +122,8 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   const bool mixed = o->precision == AGC_PREC_MIXED;
   agc::Matrix& A64 = c->solve_a64;
   agc::Matrix* A32 = mixed ? &c->solve_a : nullptr;
-  if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, n_c, AGC_F64, A64, A32);
+  if (R.am) agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32);
+  else if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, R.n_c, AGC_F64, A64, A32);
   else agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, A64, A32);
   res.nnzb = A64.nnzb;
   if (tm) tm->mark();
@@ -308,6 +313,38 @@ agc_status agc_assemble_coarse(agc_context* c, const agc_mesh* mesh, const void*
   API_END(c)
 }
 
+agc_status agc_assemble_coarse_affine(agc_context* c, const agc_mesh* mesh, const double* elem_H, const double* rest,
+                                      const double* g, const int32_t* map, int32_t n_coarse, int32_t threshold,
+                                      agc_matrix** A_c, double* g_c, int32_t* n3, int32_t* n12) {
+  API_BEGIN(c)
+  AGC_REQUIRE(mesh && elem_H && rest && map && A_c, "null pointer");
+  AGC_REQUIRE(((uintptr_t)elem_H & 15) == 0, "elem_H must be 16-byte aligned");
+  AGC_REQUIRE(n_coarse >= 1 && n_coarse <= mesh->m.n_verts, "n_coarse out of range");
+  *A_c = nullptr;
+  const int32_t n = mesh->m.n_verts;
+  agc::AffineMap am;
+  agc::affine_classify(c, n, map, n_coarse, threshold, rest, am);
+  agc_matrix* a = new agc_matrix();
+  try {
+    agc::assemble_coarse_affine(c, mesh->m, elem_H, am, a->m);
+    if (g && g_c) {
+      uint32_t* members = c->ws.get<uint32_t>("api.members", n);
+      uint32_t* mkeys = c->ws.get<uint32_t>("api.mkeys", n);
+      agc::group_members(c, n, map, n_coarse, members, mkeys);
+      agc::affine_restrict(c, n, am, members, mkeys, g, g_c);
+    }
+    AGC_HIP(hipStreamSynchronize(c->stream));
+  } catch (...) {
+    a->m.release();
+    delete a;
+    throw;
+  }
+  *A_c = a;
+  if (n3) *n3 = am.n3;
+  if (n12) *n12 = am.n12;
+  API_END(c)
+}
+
 agc_status agc_assemble_fine(agc_context* c, const agc_mesh* mesh, const void* elem_H, int32_t h_dtype,
                              int32_t out_dtype, agc_matrix** H) {
   API_BEGIN(c)
@@ -467,13 +504,19 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
     k_iota_i32<<<gsb(n), agc::kWG, 0, c->stream>>>(map_out, n);
     AGC_LAUNCH_CHECK();
   }
+  agc::AffineMap am;
+  if (R.map && o->affine_threshold > 0) {
+    agc::affine_classify(c, n, R.map, R.n_c, o->affine_threshold, p->rest, am);
+    R.am = &am;
+  }
   tm.mark();                                                   // 1
-  double* x_c = R.map ? c->ws.get<double>("solve.xc", 3 * (int64_t)R.n_c) : x;
+  double* x_c = R.map ? c->ws.get<double>("solve.xc", 3 * (int64_t)R.blocks()) : x;
   SolveResult res = coarse_solve(c, p, o, R, p->g, x_c, &tm);  // marks 2 after assembly
   tm.mark();                                                   // 3
   if (R.map) {
     agc::err_reset(c);
-    agc::prolongate(c, n, R.map, R.n_c, x_c, x);
+    if (R.am) agc::affine_prolongate(c, n, am, x_c, x);
+    else agc::prolongate(c, n, R.map, R.n_c, x_c, x);
   }
   tm.mark();                                                   // 4
   // post-coarsening (Sec. 4.3): a few fine PCG iterations from x = P x_c
@@ -510,6 +553,8 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
     info->ms_prolong = tm.ms(3, 4);
     info->spmv_launches = (int32_t)c->spmv_n;
     info->ms_spmv = (float)c->spmv_ms;
+    info->n_affine = R.am ? am.n12 : 0;
+    info->n_blocks = R.blocks();
     info->post_iters = post_done;
     info->fine_rel_res = fine_rel;
     info->fine_rel_res0 = fine_rel0;
@@ -524,7 +569,8 @@ agc_status agc_solve_backward(agc_context* c, const agc_problem* p, const agc_so
   API_BEGIN(c)
   validate_problem(p);
   validate_opts(o);
-  AGC_REQUIRE(o->post_iters == 0, "post_iters must be 0 for the derivative of the coarsened solve");
+  AGC_REQUIRE(o->post_iters == 0 && o->affine_threshold == 0,
+              "post_iters and affine_threshold must be 0 for the derivative of the coarsened solve");
   AGC_REQUIRE(x && w && dg, "null pointer");
   const agc::Mesh& mesh = p->mesh->m;
   const int32_t n = mesh.n_verts;

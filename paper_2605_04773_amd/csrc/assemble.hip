@@ -16,6 +16,8 @@
 // Only the upper triangle is reduced (the paper also accumulates only the
 // diagonal and upper blocks, Sec. 5.2 "Overall Performance"); the lower
 // triangle is the transpose of the same sums, so A_c is exactly symmetric.
+#include <string>
+
 #include "segreduce.h"
 
 namespace agc {
@@ -514,6 +516,299 @@ void assemble_coarse(agc_context* c, const Mesh& m, const void* eh, int32_t h_dt
   AGC_REQUIRE(!out32 || out_dtype == AGC_F64, "a float32 companion needs a float64 matrix");
   if (out_dtype == AGC_F64) coarse_impl<double>(c, m, eh, h_dtype, map, n_c, out, out32);
   else coarse_impl<float>(c, m, eh, h_dtype, map, n_c, out, nullptr);
+}
+
+// ------------------------------------------------ affine embedding (Eq. 4)
+//
+// A fine upper block B of vertices (i, j) adds A_u B' A_w^T to the node pair
+// of its vertices, u the vertex in the lower node (new order), w the other,
+// B' = B or B^T accordingly (as in the 3-DoF assembly).  With A = Xbar (x) I_3
+// the 3x3 sub-block (a, b) of that product is Xbar_u[a] Xbar_w[b] B'; a
+// 3-DoF node has the single sub-block a = 3 of weight 1 (supplement Alg. 4
+// flattens the same 1 / 4 / 16 sub-blocks).  Fine blocks are sorted by node
+// pair with the pairs that touch a 12-DoF node last: the others reduce as in
+// the 3-DoF assembly; those in four passes, one per row sub-block a, each
+// summing the four column sub-blocks.  The sums are flattened to 3x3 blocks
+// at (offset + a, offset + b), the upper blocks sorted, and the full
+// symmetric matrix built as before.
+
+// key: bit nb set for a pair with a 12-DoF node; below it lo * n_c + hi (new labels)
+__global__ void k_aff_keys(const int32_t* __restrict__ fr, const int32_t* __restrict__ fc, int64_t nf,
+                           const int32_t* __restrict__ map, int32_t n_c, const int32_t* __restrict__ newlab,
+                           int32_t n3, int nb, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                           unsigned* err) {
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = fr[f], j = fc[f];
+    const int32_t mi = map[i], mj = map[j];
+    if (mi < 0 || mi >= n_c || mj < 0 || mj >= n_c) {
+      atomicOr(err, kErrMap);
+      keys[f] = 0;
+      vals[f] = (uint32_t)(f * 4);
+      continue;
+    }
+    const int32_t ci = newlab[mi], cj = newlab[mj];
+    uint32_t o;
+    int32_t lo, hi;
+    if (ci < cj) { lo = ci; hi = cj; o = 0; }
+    else if (ci > cj) { lo = cj; hi = ci; o = 1; }
+    else { lo = hi = ci; o = (i == j) ? 0u : 2u; }
+    const uint64_t aff = hi >= n3 ? 1ull : 0ull;
+    keys[f] = (aff << nb) | ((uint64_t)lo * (uint64_t)n_c + (uint64_t)hi);
+    vals[f] = (uint32_t)(f * 4) | o;
+  }
+}
+
+// first position whose key has bit nb set (the caller presets *split = n)
+__global__ void k_aff_split(const uint64_t* __restrict__ keys, int64_t n, int nb, int64_t* split) {
+  const uint64_t t = 1ull << nb;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    if (keys[k] >= t && (k == 0 || keys[k - 1] < t)) *split = k;
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+
+// The sub-blocks (a, 0..3) of one fine block's contribution.
+struct AffineOp {
+  const uint32_t* payload;   // the affine part of the sorted payloads
+  const double* F;           // fine upper blocks, planes [9][nf]
+  int64_t nf;
+  const int32_t* fr;
+  const int32_t* fc;
+  const int32_t* map;
+  const int32_t* newlab;
+  int32_t n3;
+  const double* rest;
+  const int32_t* rep;        // smallest member of each (canonical) node
+  int a;                     // row sub-block of this pass
+  double* U;                 // planes [36][us]: 9 b + (3 r + s)
+  int64_t us;
+  // homogeneous rest coordinate in the node's frame (a 3-DoF node: (0, 0, 0, 1))
+  __device__ void xbar(int32_t v, bool big, double x[4]) const {
+    if (big) {
+      const int64_t r = rep[map[v]];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) x[q] = rest[3 * (int64_t)v + q] - rest[3 * r + q];
+    } else {
+      x[0] = x[1] = x[2] = 0.0;
+    }
+    x[3] = 1.0;
+  }
+  __device__ void load(int64_t k, double v[36]) const {
+    const uint32_t code = payload[k];
+    const int64_t f = code >> 2;
+    const uint32_t o = code & 3u;
+    const int32_t i = fr[f], j = fc[f];
+    double b[9], bt[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) b[q] = F[(int64_t)q * nf + f];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bt[3 * r + c] = b[3 * c + r];
+    const int32_t ci = newlab[map[i]], cj = newlab[map[j]];
+    const int32_t u = (o == 1) ? j : i, w = (o == 1) ? i : j;
+    const int32_t cu = (o == 1) ? cj : ci, cw = (o == 1) ? ci : cj;
+    double xu[4], xw[4];
+    xbar(u, cu >= n3, xu);
+    xbar(w, cw >= n3, xw);
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      if (o == 2) {
+        // i != j inside one node: (a, b) gets T(a, b) and T(b, a)^T of T = A_i B A_j^T.
+        // On the diagonal (b = a) both weights agree: w (B + B^T), formed so that the
+        // block is bitwise symmetric (a fused w1 B + w2 B^T would round its two
+        // triangles differently).
+        const double w1 = xu[a] * xw[bb], w2 = xu[bb] * xw[a];
+        if (bb == a) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) v[9 * bb + q] = w1 * (b[q] + bt[q]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) v[9 * bb + q] = w1 * b[q] + w2 * bt[q];
+        }
+      } else {
+        const double w1 = xu[a] * xw[bb];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[9 * bb + q] = w1 * (o == 1 ? bt[q] : b[q]);
+      }
+    }
+  }
+  __device__ void store(int64_t s, const double v[36]) const {
+#pragma unroll
+    for (int q = 0; q < 36; ++q) U[(int64_t)q * us + s] = v[q];
+  }
+  __device__ void add(int64_t s, const double v[36]) const {
+#pragma unroll
+    for (int q = 0; q < 36; ++q) U[(int64_t)q * us + s] += v[q];
+  }
+};
+
+__device__ __forceinline__ int aff_outputs(int32_t lo, int32_t hi, int32_t n3) {
+  if (lo < n3) return 4;        // a 3-DoF row node against a 12-DoF node
+  return lo == hi ? 10 : 16;    // one 12-DoF node (upper sub-blocks), or two
+}
+
+__global__ void k_aff_count_out(const uint64_t* __restrict__ ukeys, int64_t nua, int nb, int32_t n_c, int32_t n3,
+                                uint32_t* __restrict__ cnt) {
+  const uint64_t mask = (1ull << nb) - 1;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nua; s += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = ukeys[s] & mask;
+    cnt[s] = (uint32_t)aff_outputs((int32_t)(key / (uint64_t)n_c), (int32_t)(key % (uint64_t)n_c), n3);
+  }
+}
+
+// flat upper blocks of the affine pairs, appended after `base` entries
+__global__ void k_aff_flatten(const uint64_t* __restrict__ ukeys, int64_t nua, int nb, int32_t n_c, int32_t n3,
+                              const uint32_t* __restrict__ pos, const double* __restrict__ U0,
+                              const double* __restrict__ U1, const double* __restrict__ U2,
+                              const double* __restrict__ U3, int64_t ua_stride, int64_t base, int32_t n_flat,
+                              uint64_t* __restrict__ fkeys, double* __restrict__ UC, int64_t uc_stride) {
+  const uint64_t mask = (1ull << nb) - 1;
+  const int da[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3}, db[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nua; s += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = ukeys[s] & mask;
+    const int32_t lo = (int32_t)(key / (uint64_t)n_c), hi = (int32_t)(key % (uint64_t)n_c);
+    const int cnt = aff_outputs(lo, hi, n3);
+    const int64_t off_lo = lo < n3 ? lo : n3 + 4 * (int64_t)(lo - n3);
+    const int64_t off_hi = n3 + 4 * (int64_t)(hi - n3);
+    for (int t = 0; t < cnt; ++t) {
+      int a, b;
+      if (cnt == 4) { a = 3; b = t; }
+      else if (cnt == 10) { a = da[t]; b = db[t]; }
+      else { a = t >> 2; b = t & 3; }
+      const int64_t r = lo < n3 ? off_lo : off_lo + a;
+      const int64_t c = off_hi + b;
+      const double* U = a == 0 ? U0 : (a == 1 ? U1 : (a == 2 ? U2 : U3));
+      const int64_t p = base + pos[s] + t;
+      fkeys[p] = (uint64_t)r * (uint64_t)n_flat + (uint64_t)c;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) UC[(int64_t)q * uc_stride + p] = U[(int64_t)(9 * b + q) * ua_stride + s];
+    }
+  }
+}
+
+// the 3-DoF pairs: flat key (labels are flat) and their sums
+__global__ void k_aff_plain(const uint64_t* __restrict__ ukeys, int64_t nu9, int32_t n_c, int32_t n_flat,
+                            const double* __restrict__ U9, int64_t u9_stride, uint64_t* __restrict__ fkeys,
+                            double* __restrict__ UC, int64_t uc_stride) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nu9; s += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = ukeys[s];
+    const uint64_t lo = key / (uint64_t)n_c, hi = key % (uint64_t)n_c;
+    fkeys[s] = lo * (uint64_t)n_flat + hi;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) UC[(int64_t)q * uc_stride + s] = U9[(int64_t)q * u9_stride + s];
+  }
+}
+
+// sorted flat keys -> (row, col) and the values gathered into sorted order
+__global__ void k_aff_sorted(const uint64_t* __restrict__ sk, const uint32_t* __restrict__ perm, int64_t nu,
+                             int32_t n_flat, const double* __restrict__ UC, int64_t uc_stride,
+                             int32_t* __restrict__ ur, int32_t* __restrict__ uc, double* __restrict__ US) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nu; k += (int64_t)gridDim.x * blockDim.x) {
+    ur[k] = (int32_t)(sk[k] / (uint64_t)n_flat);
+    uc[k] = (int32_t)(sk[k] % (uint64_t)n_flat);
+    const int64_t p = perm[k];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) US[(int64_t)q * nu + k] = UC[(int64_t)q * uc_stride + p];
+  }
+}
+
+void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* eh, const AffineMap& am, Matrix& out,
+                            Matrix* out32) {
+  const int64_t nf = m.nf;
+  const int32_t n_c = am.n_c, n3 = am.n3, n_flat = am.n_flat;
+  double* F = fine_upper<double>(c, m, eh, AGC_F64);
+  uint64_t* k1 = c->ws.get<uint64_t>("asm.k1", nf);
+  uint64_t* k2 = c->ws.get<uint64_t>("asm.k2", nf);
+  uint32_t* v1 = c->ws.get<uint32_t>("asm.v1", nf);
+  uint32_t* v2 = c->ws.get<uint32_t>("asm.v2", nf);
+  const int nb = bits_for((uint64_t)n_c * (uint64_t)n_c - 1);
+  err_reset(c);
+  k_aff_keys<<<grid_stride_blocks(nf), kWG, 0, c->stream>>>((const int32_t*)m.fu_row.p, (const int32_t*)m.fu_col.p,
+                                                           nf, am.map, n_c, am.newlab, n3, nb, k1, v1, c->d_err);
+  AGC_LAUNCH_CHECK();
+  const bool alt = radix_sort_u64(c, k1, v1, k2, v2, nf, nb + 1, "aasm.sort");
+  uint64_t* sk = alt ? k2 : k1;
+  uint32_t* sv = alt ? v2 : v1;
+  uint64_t* uk = alt ? k1 : k2;   // free buffer for the unique keys
+  int64_t* dsplit = c->ws.get<int64_t>("aasm.split", 1);
+  k_set_i64<<<1, 1, 0, c->stream>>>(dsplit, nf);
+  k_aff_split<<<grid_stride_blocks(nf), kWG, 0, c->stream>>>(sk, nf, nb, dsplit);
+  AGC_LAUNCH_CHECK();
+  int64_t split = 0;
+  AGC_HIP(hipMemcpyAsync(&split, dsplit, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  AGC_HIP(hipStreamSynchronize(c->stream));
+  // the 3-DoF pairs
+  double* U9 = c->ws.get<double>("aasm.U9", 9 * nf);   // CoarseOp writes planes of stride nf
+  int64_t nu9 = 0;
+  if (split > 0) {
+    CoarseOp<double> op{sv, F, nf, U9};
+    nu9 = seg_reduce<9, double, uint64_t, CoarseOp<double>>(c, sk, split, op, uk, true, "aasm.seg9");
+  }
+  // the pairs with a 12-DoF node: four passes of four sub-blocks
+  const int64_t na = nf - split;
+  int64_t nua = 0;
+  double* UA[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint64_t* uka = c->ws.get<uint64_t>("aasm.uka", na > 0 ? na : 1);
+  if (na > 0) {
+    for (int a = 0; a < 4; ++a) {
+      UA[a] = c->ws.get<double>("aasm.UA" + std::to_string(a), 36 * na);
+      AffineOp op{sv + split, F, nf, (const int32_t*)m.fu_row.p, (const int32_t*)m.fu_col.p, am.map, am.newlab,
+                  n3, am.rest, am.rep, a, UA[a], na};
+      const int64_t cnt = seg_reduce<36, double, uint64_t, AffineOp>(c, sk + split, na, op, a == 0 ? uka : nullptr,
+                                                                      a == 0, "aasm.seg36");
+      if (a == 0) nua = cnt;
+    }
+  }
+  // flat upper blocks: the 3-DoF ones, then the flattened affine ones
+  uint32_t* acnt = c->ws.get<uint32_t>("aasm.acnt", nua + 1);
+  int64_t n_aff_out = 0;
+  if (nua > 0) {
+    k_aff_count_out<<<grid_stride_blocks(nua), kWG, 0, c->stream>>>(uka, nua, nb, n_c, n3, acnt);
+    AGC_LAUNCH_CHECK();
+    scan_u32(c, acnt, acnt, nua, "aasm.scan");
+    uint32_t t = 0;
+    AGC_HIP(hipMemcpyAsync(&t, acnt + nua, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    AGC_HIP(hipStreamSynchronize(c->stream));
+    n_aff_out = t;
+  }
+  const int64_t nu = nu9 + n_aff_out;
+  AGC_REQUIRE(nu >= 1, "empty coarse pattern");
+  uint64_t* fk1 = c->ws.get<uint64_t>("aasm.fk1", nu);
+  uint64_t* fk2 = c->ws.get<uint64_t>("aasm.fk2", nu);
+  uint32_t* fp1 = c->ws.get<uint32_t>("aasm.fp1", nu);
+  uint32_t* fp2 = c->ws.get<uint32_t>("aasm.fp2", nu);
+  double* UC = c->ws.get<double>("aasm.UC", 9 * nu);
+  if (nu9 > 0) {
+    k_aff_plain<<<grid_stride_blocks(nu9), kWG, 0, c->stream>>>(uk, nu9, n_c, n_flat, U9, nf, fk1, UC, nu);
+    AGC_LAUNCH_CHECK();
+  }
+  if (nua > 0) {
+    k_aff_flatten<<<grid_stride_blocks(nua), kWG, 0, c->stream>>>(uka, nua, nb, n_c, n3, acnt, UA[0], UA[1], UA[2],
+                                                                 UA[3], na, nu9, n_flat, fk1, UC, nu);
+    AGC_LAUNCH_CHECK();
+  }
+  k_iota_u32<<<grid_stride_blocks(nu), kWG, 0, c->stream>>>(fp1, nu);
+  AGC_LAUNCH_CHECK();
+  const bool falt = radix_sort_u64(c, fk1, fp1, fk2, fp2, nu, bits_for((uint64_t)n_flat * (uint64_t)n_flat - 1),
+                                   "aasm.fsort");
+  int32_t* ur = c->ws.get<int32_t>("aasm.ur", nu);
+  int32_t* ucol = c->ws.get<int32_t>("aasm.uc", nu);
+  double* US = c->ws.get<double>("aasm.US", 9 * nu);
+  k_aff_sorted<<<grid_stride_blocks(nu), kWG, 0, c->stream>>>(falt ? fk2 : fk1, falt ? fp2 : fp1, nu, n_flat, UC, nu,
+                                                             ur, ucol, US);
+  AGC_LAUNCH_CHECK();
+  out.reserve(n_flat, 2 * nu, AGC_F64);
+  uint32_t* src = c->ws.get<uint32_t>("aasm.src", 2 * nu);
+  build_full(c, n_flat, nu, ur, ucol, FullPattern{out.rp(), out.ci(), out.ri(), src, out.dg()}, "aasm.full");
+  int32_t nnz = 0;
+  AGC_HIP(hipMemcpyAsync(&nnz, out.rp() + n_flat, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  err_throw(err_fetch(c));
+  out.set_nnzb(nnz);
+  float* v32 = companion32(out, out32);
+  k_fill_vals<double><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>(src, nnz, US, nu, (double*)out.vals.p, out.stride,
+                                                                   v32);
+  AGC_LAUNCH_CHECK();
 }
 
 // -------------------------------------------------------- adjoint outer product

@@ -113,6 +113,29 @@ void restrict_sorted(agc_context* c, int32_t n, int32_t n_c, const uint32_t* mem
 // x[v] = x_c[map[v]]; a map value outside [0, n_c) sets kErrMap and writes 0
 void prolongate(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, const double* x_c, double* x);
 
+// --------------------------------------------------------- affine embedding
+// Coarse nodes with more than `threshold` members carry 12 DoF (Eq. 4):
+// x_f = sum_k Xbar_f[k] q_c[k] over four 3-blocks k, Xbar_f = (X, Y, Z, 1) the
+// rest position in the aggregate's frame (origin at its smallest-id member).
+// New node order: 3-DoF nodes first (canonical order), then 12-DoF nodes; a
+// node's first flat 3-block is offset[c] (3-DoF: its new label; 12-DoF:
+// n3 + 4 (label - n3)).
+struct AffineMap {
+  int32_t n_c = 0, n3 = 0, n12 = 0, n_flat = 0;
+  const int32_t* map = nullptr;    // [n] canonical labels
+  const double* rest = nullptr;    // [n][3] rest positions
+  int32_t* newlab = nullptr;       // [n_c]
+  int32_t* offset = nullptr;       // [n_c]
+  int32_t* rep = nullptr;          // [n_c] smallest member id
+};
+void affine_classify(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, int32_t threshold,
+                     const double* rest, AffineMap& am);
+// v_flat = P^T v (members/mkeys from group_members)
+void affine_restrict(agc_context* c, int32_t n, const AffineMap& am, const uint32_t* members,
+                     const uint32_t* mkeys, const double* v, double* v_flat);
+// x = P x_flat; a map value outside [0, n_c) sets kErrMap and writes 0
+void affine_prolongate(agc_context* c, int32_t n, const AffineMap& am, const double* x_flat, double* x);
+
 // ------------------------------------------------------------- assembly
 void mesh_build(agc_context* c, Mesh& m, int32_t n_verts, int64_t n_elems, const int32_t* ev);
 // out32 (float64 output only, may be null) receives the same matrix rounded
@@ -122,6 +145,10 @@ void assemble_fine(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_
 void assemble_coarse(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
                      const int32_t* map, int32_t n_c, int32_t out_dtype, Matrix& out,
                      Matrix* out32 = nullptr);
+// A = P^T H P in the flat 3-block layout of `am` (float64 sums; out32 as for
+// assemble_coarse)
+void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* elem_h, const AffineMap& am,
+                            Matrix& out, Matrix* out32 = nullptr);
 // dH_e = -(dg_e)(x_e)^T
 void elem_outer(agc_context* c, const Mesh& m, const double* dg, const double* x, double* dh);
 

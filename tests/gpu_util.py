@@ -55,11 +55,13 @@ class Dev:
         self.eh = self.t(p["elem_H"], torch.float64)
         self.eh32 = self.eh.to(torch.float32) if f32 else None
         self.g = self.t(p["g"], torch.float64)
+        self.rest = self.t(p["pos"], torch.float64)
         self.mesh = agc.agc_mesh_create(ctx, p["n_verts"], self.ev)
 
     def problem(self, tags=None):
         agc = binding()
-        return agc.make_problem(self.mesh, self.edges, self.tags if tags is None else tags, self.eh, self.g)
+        return agc.make_problem(self.mesh, self.edges, self.tags if tags is None else tags, self.eh, self.g,
+                                self.rest)
 
 
 def to_scipy(mat) -> sp.csr_matrix:

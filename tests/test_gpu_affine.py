@@ -1,0 +1,162 @@
+"""GPU parity of the adaptive affine embedding (Sec. 4.2, Eq. 4; supplement Alg. 3-4)
+against oracle/affine.py.
+
+Pattern: the set of 3x3 blocks equals the oracle's block incidence P_b^T H_b P_b
+(bit-exact).  Values: |A_gpu - A_oracle| <= gamma_D (|P|^T |H| |P|) entrywise,
+D the depth of the summation tree; g_c likewise.  Solves: FP64 oracle relative
+residual <= 1e-8 (asked 1e-10); mixed error <= 1e-5 against the oracle's
+direct solve.  With no aggregate above the threshold the path equals the
+3-DoF one bit for bit."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import affine as oaff
+from oracle import aggregate as oagg
+from oracle import galerkin as ogal
+from oracle import solve as osol
+from tests.gpu_util import Dev, binding, bsr_numpy, gamma, log, problem
+
+pytestmark = pytest.mark.gpu
+
+THR = 32
+_devs = {}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    agc = binding()
+    c = agc.Context(0)
+    yield c
+    c.close()
+
+
+def dev(ctx, name):
+    if name not in _devs:
+        _devs[name] = Dev(ctx, problem(name))
+    return _devs[name]
+
+
+def _block_incidence(p, m, cls):
+    """n x n_flat 0/1 matrix: fine vertex f -> the flat 3-blocks its node owns."""
+    n = p["n_verts"]
+    big = cls["big"][m]
+    off = cls["offset"][m]
+    rows = [np.flatnonzero(~big)]
+    cols = [off[~big]]
+    f = np.flatnonzero(big)
+    for k in range(4):
+        rows.append(f)
+        cols.append(off[f] + k)
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    return sp.csr_matrix((np.ones(r.size), (r, c)), shape=(n, cls["n_flat"]))
+
+
+def _fine_block_pattern(p):
+    ev = p["elem_verts"].astype(np.int64)
+    a, b = np.meshgrid(np.arange(4), np.arange(4), indexing="ij")
+    r = ev[:, a.ravel()].ravel()
+    c = ev[:, b.ravel()].ravel()
+    n = p["n_verts"]
+    return sp.csr_matrix((np.ones(r.size), (r, c)), shape=(n, n))
+
+
+@pytest.mark.parametrize("name", ["c1", "c4", "c3"])
+def test_assembly_matches_oracle(ctx, name):
+    agc = binding()
+    d = dev(ctx, name)
+    p = d.p
+    log(f"[aff] assemble {name}")
+    mp, nc = agc.agc_aggregate(ctx, p["n_verts"], d.edges, d.tags)
+    A, g_c, n3, n12 = agc.agc_assemble_coarse_affine(ctx, d.mesh, d.eh, d.rest, d.g, mp, nc, THR)
+    m = mp.cpu().numpy()
+    cls = oaff.classify(m, nc, THR)
+    assert (n3, n12) == (cls["n3"], cls["n12"]) and n12 >= 1
+    rp, ci, vals = bsr_numpy(A)
+    # pattern: exactly the blocks reachable through the fine block pattern
+    bi = _block_incidence(p, m, cls)
+    want = (bi.T @ _fine_block_pattern(p) @ bi).tocsr()
+    want.sort_indices()
+    assert np.array_equal(rp, want.indptr) and np.array_equal(ci, want.indices)
+    # values within the summation bound
+    a_ref, b_ref, _, pm = oaff.coarse_system(p, m, nc, THR)
+    pa = abs(pm)
+    h_abs = ogal.fine_hessian(p["n_verts"], p["elem_verts"], np.abs(p["elem_H"]))
+    a_abs = (pa.T @ h_abs @ pa).tocsr()
+    nb = cls["n_flat"]
+    got = sp.bsr_matrix((vals, ci, rp), shape=(3 * nb, 3 * nb)).tocsr()
+    diff = abs(got - a_ref)
+    bound = gamma(256) * a_abs
+    excess = (diff - bound).tocsr()
+    assert excess.max() <= 0.0 if excess.nnz else True
+    sym = abs(got - got.T)
+    assert sym.max() == 0.0 if sym.nnz else True
+    gc = g_c.cpu().numpy()
+    g_abs = (pa.T @ np.abs(p["g"]).reshape(-1)).reshape(-1, 3)
+    assert (np.abs(gc - b_ref) <= gamma(64) * g_abs).all()
+    log(f"   n3={n3} n12={n12} blocks={nb} nnzb={A.nnzb}")
+
+
+def _affine_reference(p, threshold):
+    m, nc = oagg.components(p["n_verts"], p["edges"], p["tags"])
+    a_c, b_c, cls, pm = oaff.coarse_system(p, m, nc, threshold)
+    x_c = osol.solve_sparse(a_c, b_c.reshape(-1))
+    return m, cls, a_c, b_c, pm, oaff.prolongate(pm, x_c)
+
+
+@pytest.mark.parametrize("name", ["c1", "c4", "c3"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_matches_oracle(ctx, name, precision):
+    import torch
+    agc = binding()
+    d = dev(ctx, name)
+    p = d.p
+    log(f"[aff] solve {name} {precision}")
+    m, cls, a_c, b_c, pm, x_ref = _affine_reference(p, THR)
+    x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=ctx.device)
+    mp = torch.empty(p["n_verts"], dtype=torch.int32, device=ctx.device)
+    prec = agc.AGC_PREC_MIXED if precision == "mixed" else agc.AGC_PREC_FP64
+    rtol = 1e-10 if precision == "fp64" else 1e-7
+    info = agc.agc_solve(ctx, d.problem(), agc.make_opts(precision=prec, rtol=rtol, max_iter=50000,
+                                                          affine_threshold=THR), x, mp)
+    xh = x.cpu().numpy()
+    assert np.array_equal(mp.cpu().numpy(), m)
+    assert info.n_affine == cls["n12"] and info.n_blocks == cls["n_flat"]
+    err = np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref)
+    log(f"   n12={info.n_affine} iters={info.pcg_iters} rel_res={info.rel_res:.2e} err={err:.2e}")
+    if precision == "fp64":
+        # the coarse residual of the GPU solution: with x = P x_c,
+        # P^T (g - H x) = b_c - A_c x_c
+        h = ogal.fine_hessian(p["n_verts"], p["elem_verts"], p["elem_H"])
+        r_c = pm.T @ (p["g"].reshape(-1) - h @ xh.reshape(-1))
+        rel = np.linalg.norm(r_c) / np.linalg.norm(b_c)
+        log(f"   oracle coarse residual {rel:.2e}")
+        assert rel <= 1e-8, rel
+    assert err <= 1e-5
+
+
+def test_large_threshold_equals_plain_path(ctx):
+    import torch
+    agc = binding()
+    d = dev(ctx, "c4")
+    p = d.p
+    outs = []
+    for thr in (0, 10 ** 9):
+        x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=ctx.device)
+        info = agc.agc_solve(ctx, d.problem(), agc.make_opts(rtol=1e-9, affine_threshold=thr), x, None)
+        outs.append((x.cpu().numpy(), info.n_affine, info.n_blocks, info.n_coarse))
+    assert outs[1][1] == 0 and outs[1][2] == outs[1][3]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+def test_affine_needs_rest_and_no_backward(ctx):
+    import torch
+    agc = binding()
+    d = dev(ctx, "c1")
+    p = d.p
+    prob = agc.make_problem(d.mesh, d.edges, d.tags, d.eh, d.g)      # no rest positions
+    x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=ctx.device)
+    with pytest.raises(agc.AgcError):
+        agc.agc_solve(ctx, prob, agc.make_opts(affine_threshold=THR), x, None)
+    with pytest.raises(agc.AgcError):
+        agc.agc_solve_backward(ctx, d.problem(), agc.make_opts(affine_threshold=THR), None, 0, None, None, None, None)

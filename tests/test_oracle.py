@@ -355,3 +355,101 @@ def test_post_coarsen_is_cg_on_the_fine_system():
     assert np.linalg.norm(x - x_star) <= 1e-9 * np.linalg.norm(x_star)
     x, its = _m.post_coarsen(p, x0, 2000, rtol=1e-13)
     assert np.linalg.norm(x - x_star) <= 1e-8 * np.linalg.norm(x_star)
+
+
+# ------------------------------------------------------- affine embedding
+
+def _affine_case(name="c1", threshold=32):
+    from oracle import affine
+    p = synth.make_config(name)
+    m, n_c = aggregate.components(p["n_verts"], p["edges"], p["tags"])
+    return p, m, n_c, affine.coarse_system(p, m, n_c, threshold)
+
+
+def test_affine_reproduces_its_range():
+    """Galerkin reproduction, independent of how P^T H P is formed: if the fine
+    solution lies in range(P) (affine on every 12-DoF aggregate, constant on
+    every other), the coarsened solve returns it exactly."""
+    from oracle import affine
+    p, m, n_c, (a_c, b_c, cls, pm) = _affine_case()
+    assert cls["n12"] >= 1 and cls["n3"] >= 1
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(3 * cls["n_flat"])
+    x_star = pm @ y
+    h = galerkin.fine_hessian(p["n_verts"], p["elem_verts"], p["elem_H"])
+    q = dict(p, g=(h @ x_star).reshape(-1, 3))
+    a2, b2, _, pm2 = affine.coarse_system(q, m, n_c, 32)
+    x_c = solve.solve_dense(a2.toarray(), b2.reshape(-1))
+    x = affine.prolongate(pm2, x_c)
+    assert np.linalg.norm(x.reshape(-1) - x_star) <= 1e-10 * np.linalg.norm(x_star)
+
+
+def test_affine_moments_and_limits():
+    """P^T P of a 12-DoF node is (sum_f Xbar_f Xbar_f^T) (x) I_3 (its rest moments);
+    a threshold above every aggregate gives the plain 3-DoF system; the 12-DoF
+    span contains the plain one (translations are the k = 3 block)."""
+    from oracle import affine
+    p, m, n_c, (a_c, b_c, cls, pm) = _affine_case()
+    ptp = (pm.T @ pm).toarray()
+    c = int(np.flatnonzero(cls["big"])[0])
+    o = int(cls["offset"][c])
+    mem = np.flatnonzero(m == c)
+    xb = np.concatenate([p["pos"][mem] - p["pos"][mem.min()], np.ones((mem.size, 1))], axis=1)
+    mom = xb.T @ xb
+    blk = ptp[3 * o: 3 * o + 12, 3 * o: 3 * o + 12]
+    assert np.allclose(blk, np.kron(mom, np.eye(3)), rtol=1e-13, atol=1e-13)
+    a0, b0, cls0, _ = affine.coarse_system(p, m, n_c, 10 ** 9)
+    assert cls0["n12"] == 0
+    a_ref, b_ref = galerkin.coarse_system(p["n_verts"], p["elem_verts"], p["elem_H"], p["g"], m, n_c)
+    assert abs(a0 - a_ref).max() <= 1e-9 * abs(a_ref).max() and np.allclose(b0, b_ref, rtol=1e-13, atol=1e-12)
+    # energy: the affine-enriched solve lowers the quadratic model's minimum (a larger subspace)
+    def energy(a, b):
+        x = solve.solve_dense(a.toarray(), b.reshape(-1))
+        return -0.5 * float(b.reshape(-1) @ x)
+    assert energy(a_c, b_c) <= energy(a0, b0) + 1e-12 * abs(energy(a0, b0))
+    # symmetric positive definite
+    ev = np.linalg.eigvalsh(a_c.toarray())
+    assert ev.min() > 0 and abs(a_c - a_c.T).max() <= 1e-9 * abs(a_c).max()
+
+
+def test_affine_threshold_is_strict():
+    """Only aggregates with MORE members than the threshold get 12 DoF (Eq. 4 text)."""
+    from oracle import affine
+    p = synth.make_config("c1")
+    m, n_c = aggregate.components(p["n_verts"], p["edges"], p["tags"])
+    big = int(np.bincount(m).max())
+    assert affine.classify(m, n_c, big)["n12"] == 0
+    assert affine.classify(m, n_c, big - 1)["n12"] >= 1
+
+
+def test_affine_mutants_trip_the_pins():
+    """Planted mistakes in a copy of the affine prolongation (the homogeneous
+    coordinate in front; the translation block dropped) each break the moment pin."""
+    from oracle import affine
+    p = synth.make_config("c1")
+    m, n_c = aggregate.components(p["n_verts"], p["edges"], p["tags"])
+    cls = affine.classify(m, n_c, 32)
+    c = int(np.flatnonzero(cls["big"])[0])
+    o = int(cls["offset"][c])
+    mem = np.flatnonzero(m == c)
+    xb = np.concatenate([p["pos"][mem] - p["pos"][mem.min()], np.ones((mem.size, 1))], axis=1)
+    want = np.kron(xb.T @ xb, np.eye(3))
+
+    def moments_ok(pm):
+        blk = (pm.T @ pm).toarray()[3 * o: 3 * o + 12, 3 * o: 3 * o + 12]
+        return np.allclose(blk, want, rtol=1e-13, atol=1e-13)
+
+    assert moments_ok(affine.prolongation(m, p["pos"], cls))
+    good = affine.prolongation(m, p["pos"], cls).tocoo()
+    rows, cols, vals = good.row, good.col, good.data.copy()
+    # 1: (1, X, Y, Z) order: swap the weights of blocks k = 0 and k = 3
+    blockk = (cols // 3 - cls["offset"][m[rows // 3]])
+    in_big = cls["big"][m[rows // 3]]
+    v1 = vals.copy()
+    sel0, sel3 = in_big & (blockk == 0), in_big & (blockk == 3)
+    v1[sel0], v1[sel3] = vals[sel3], vals[sel0]
+    assert not moments_ok(sp.csr_matrix((v1, (rows, cols)), shape=good.shape))
+    # 2: translation block dropped
+    v2 = vals.copy()
+    v2[sel3] = 0.0
+    assert not moments_ok(sp.csr_matrix((v2, (rows, cols)), shape=good.shape))
