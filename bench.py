@@ -159,7 +159,7 @@ def main():
     mesh = agc.agc_mesh_create(ctx, p["n_verts"], ev)
     setup_ms = (time.perf_counter() - t0) * 1e3
     log(f"[bench] mesh setup (static, once per mesh) {setup_ms:.1f} ms")
-    prob = agc.make_problem(mesh, edges, tags, eh, g)
+    prob = agc.make_problem(mesh, edges, tags, eh, g, t(p["pos"], torch.float64))
     x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=dev)
     mp = torch.empty(p["n_verts"], dtype=torch.int32, device=dev)
 
@@ -210,6 +210,14 @@ def main():
         f"{pinfo.fine_rel_res0:.2e} -> {pinfo.fine_rel_res:.2e}")
     extra["post_coarsening"] = {"iters": pinfo.post_iters, "ms_per_solve": round(ms_post, 4),
                                 "fine_rel_res_before": pinfo.fine_rel_res0, "fine_rel_res_after": pinfo.fine_rel_res}
+    # the paper's main variant: 12-DoF affine nodes for aggregates of more than 32 vertices
+    aff = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, affine_threshold=32)
+    ms_aff, ainfo = time_steps(aff, max(3, args.steps // 2), 1, torch)
+    log(f"[bench] with affine embedding (> 32 members): {ms_aff:.3f} ms/solve, {ainfo.n_affine} affine nodes, "
+        f"{ainfo.n_blocks} block rows, pcg_iters={ainfo.pcg_iters} rel_res={ainfo.rel_res:.2e}")
+    extra["affine_embedding"] = {"threshold": 32, "ms_per_solve": round(ms_aff, 4), "n_affine": ainfo.n_affine,
+                                 "block_rows": ainfo.n_blocks, "pcg_iters": ainfo.pcg_iters,
+                                 "rel_res_fp64": ainfo.rel_res}
     # the step before the map: Green-strain-increment tags for two synthetic iterates
     n_tets = int(p.get("n_tets", p["elem_verts"].shape[0]))
     tagger = agc.agc_tagger_create(ctx, p["n_verts"], ev[:n_tets].contiguous(), t(p["pos"], torch.float64), edges)
