@@ -281,25 +281,17 @@ void prolongate(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, cons
 
 // ------------------------------------------------------- affine embedding
 
-__global__ void k_aff_init(uint32_t* __restrict__ cnt, int32_t* __restrict__ rep, int32_t n_c) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_c; c += (int64_t)gridDim.x * blockDim.x) {
-    cnt[c] = 0;
-    rep[c] = INT32_MAX;
-  }
-}
-
-// members per node and the smallest member (integer atomics: the result does
-// not depend on their order)
-__global__ void k_aff_count(const int32_t* __restrict__ map, int32_t n, int32_t n_c, uint32_t* __restrict__ cnt,
-                            int32_t* __restrict__ rep, unsigned* err) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = map[v];
-    if (c < 0 || c >= n_c) {
-      atomicOr(err, kErrMap);
-      continue;
+// From the members sorted by (node, id): the first member of each node (its
+// smallest id) and the member counts, without atomics.
+__global__ void k_aff_segments(const uint32_t* __restrict__ members, const uint32_t* __restrict__ mkeys, int32_t n,
+                               int32_t n_c, uint32_t* __restrict__ start, int32_t* __restrict__ rep) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = mkeys[k];
+    if (k == 0 || mkeys[k - 1] != c) {
+      start[c] = (uint32_t)k;
+      rep[c] = (int32_t)members[k];
     }
-    atomicAdd(cnt + c, 1u);
-    atomicMin(rep + c, (int32_t)v);
+    if (k == n - 1) start[n_c] = (uint32_t)n;
   }
 }
 
@@ -310,10 +302,10 @@ __device__ __forceinline__ double aff_coord(const double* __restrict__ rest, con
 }
 
 // flag12[c] = (members > threshold); flag3[c] = the complement
-__global__ void k_aff_flags(const uint32_t* __restrict__ cnt, int32_t n_c, int32_t threshold,
+__global__ void k_aff_flags(const uint32_t* __restrict__ start, int32_t n_c, int32_t threshold,
                             uint32_t* __restrict__ f3, uint32_t* __restrict__ f12) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_c; c += (int64_t)gridDim.x * blockDim.x) {
-    const bool big = cnt[c] > (uint32_t)threshold;
+    const bool big = start[c + 1] - start[c] > (uint32_t)threshold;
     f3[c] = big ? 0u : 1u;
     f12[c] = big ? 1u : 0u;
   }
@@ -334,8 +326,8 @@ __global__ void k_aff_labels(const uint32_t* __restrict__ r3, const uint32_t* __
   }
 }
 
-void affine_classify(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, int32_t threshold,
-                     const double* rest, AffineMap& am) {
+void affine_classify(agc_context* c, int32_t n, const int32_t* map, const uint32_t* members, const uint32_t* mkeys,
+                     int32_t n_c, int32_t threshold, const double* rest, AffineMap& am) {
   AGC_REQUIRE(threshold >= 0, "affine threshold < 0");
   AGC_REQUIRE(rest, "rest positions are required for the affine embedding");
   am.n_c = n_c;
@@ -344,15 +336,15 @@ void affine_classify(agc_context* c, int32_t n, const int32_t* map, int32_t n_c,
   am.newlab = c->ws.get<int32_t>("aff.newlab", n_c);
   am.offset = c->ws.get<int32_t>("aff.offset", n_c);
   am.rep = c->ws.get<int32_t>("aff.rep", n_c);
-  uint32_t* cnt = c->ws.get<uint32_t>("aff.cnt", n_c);
+  uint32_t* start = c->ws.get<uint32_t>("aff.start", n_c + 1);
   uint32_t* f3 = c->ws.get<uint32_t>("aff.f3", n_c + 1);
   uint32_t* f12 = c->ws.get<uint32_t>("aff.f12", n_c + 1);
   uint32_t* r3 = c->ws.get<uint32_t>("aff.r3", n_c + 1);
   uint32_t* r12 = c->ws.get<uint32_t>("aff.r12", n_c + 1);
   err_reset(c);
-  k_aff_init<<<gs_blocks(n_c), kWG, 0, c->stream>>>(cnt, am.rep, n_c);
-  k_aff_count<<<gs_blocks(n), kWG, 0, c->stream>>>(map, n, n_c, cnt, am.rep, c->d_err);
-  k_aff_flags<<<gs_blocks(n_c), kWG, 0, c->stream>>>(cnt, n_c, threshold, f3, f12);
+  // every label in [0, n_c) has members (a canonical map), so every start is written
+  k_aff_segments<<<gs_blocks(n), kWG, 0, c->stream>>>(members, mkeys, n, n_c, start, am.rep);
+  k_aff_flags<<<gs_blocks(n_c), kWG, 0, c->stream>>>(start, n_c, threshold, f3, f12);
   AGC_LAUNCH_CHECK();
   scan_u32(c, f3, r3, n_c, "aff.s3");
   scan_u32(c, f12, r12, n_c, "aff.s12");

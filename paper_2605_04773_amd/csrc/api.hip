@@ -322,17 +322,16 @@ agc_status agc_assemble_coarse_affine(agc_context* c, const agc_mesh* mesh, cons
   AGC_REQUIRE(n_coarse >= 1 && n_coarse <= mesh->m.n_verts, "n_coarse out of range");
   *A_c = nullptr;
   const int32_t n = mesh->m.n_verts;
+  uint32_t* members = c->ws.get<uint32_t>("api.members", n);
+  uint32_t* mkeys = c->ws.get<uint32_t>("api.mkeys", n);
+  agc::group_members(c, n, map, n_coarse, members, mkeys);
+  agc::err_throw(agc::err_fetch(c));
   agc::AffineMap am;
-  agc::affine_classify(c, n, map, n_coarse, threshold, rest, am);
+  agc::affine_classify(c, n, map, members, mkeys, n_coarse, threshold, rest, am);
   agc_matrix* a = new agc_matrix();
   try {
     agc::assemble_coarse_affine(c, mesh->m, elem_H, am, a->m);
-    if (g && g_c) {
-      uint32_t* members = c->ws.get<uint32_t>("api.members", n);
-      uint32_t* mkeys = c->ws.get<uint32_t>("api.mkeys", n);
-      agc::group_members(c, n, map, n_coarse, members, mkeys);
-      agc::affine_restrict(c, n, am, members, mkeys, g, g_c);
-    }
+    if (g && g_c) agc::affine_restrict(c, n, am, members, mkeys, g, g_c);
     AGC_HIP(hipStreamSynchronize(c->stream));
   } catch (...) {
     a->m.release();
@@ -506,7 +505,7 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   }
   agc::AffineMap am;
   if (R.map && o->affine_threshold > 0) {
-    agc::affine_classify(c, n, R.map, R.n_c, o->affine_threshold, p->rest, am);
+    agc::affine_classify(c, n, R.map, R.members, R.mkeys, R.n_c, o->affine_threshold, p->rest, am);
     R.am = &am;
   }
   tm.mark();                                                   // 1

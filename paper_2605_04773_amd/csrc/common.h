@@ -171,6 +171,10 @@ __device__ __forceinline__ int32_t dpp_move(int32_t old, int32_t x) {
   return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWS, 0xf, false);
 }
 template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move(float old, float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_move(double old, double x) {
   const int32_t lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(x), CTRL, ROWS, 0xf, false);
   const int32_t hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(x), CTRL, ROWS, 0xf, false);
@@ -179,12 +183,12 @@ __device__ __forceinline__ double dpp_move(double old, double x) {
 
 // One Hillis-Steele step of a segmented inclusive scan: add the value of the
 // source lane when it carries the same key.  Keys never equal INT32_MIN.
-template <int CTRL, int ROWS, int N>
-__device__ __forceinline__ void seg_scan_step(int32_t key, double (&v)[N]) {
+template <int CTRL, int ROWS, int N, class T>
+__device__ __forceinline__ void seg_scan_step(int32_t key, T (&v)[N]) {
   const int32_t ku = dpp_move<CTRL, ROWS>((int32_t)INT32_MIN, key);
-  double vu[N];
+  T vu[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) vu[i] = dpp_move<CTRL, ROWS>(0.0, v[i]);
+  for (int i = 0; i < N; ++i) vu[i] = dpp_move<CTRL, ROWS>((T)0, v[i]);
   if (ku == key) {
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] += vu[i];
@@ -195,8 +199,8 @@ __device__ __forceinline__ void seg_scan_step(int32_t key, double (&v)[N]) {
 // being runs of equal, non-decreasing keys: shifts 1, 2, 4, 8 inside each
 // row of 16 lanes, then row 0 -> 1 and 2 -> 3, then lane 31 -> rows 2, 3.
 // The order of additions is fixed.
-template <int N>
-__device__ __forceinline__ void wave_seg_scan(int32_t key, double (&v)[N]) {
+template <int N, class T>
+__device__ __forceinline__ void wave_seg_scan(int32_t key, T (&v)[N]) {
   seg_scan_step<kDppRowShr1, 0xf>(key, v);
   seg_scan_step<kDppRowShr2, 0xf>(key, v);
   seg_scan_step<kDppRowShr4, 0xf>(key, v);

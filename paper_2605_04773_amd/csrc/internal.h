@@ -128,8 +128,10 @@ struct AffineMap {
   int32_t* offset = nullptr;       // [n_c]
   int32_t* rep = nullptr;          // [n_c] smallest member id
 };
-void affine_classify(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, int32_t threshold,
-                     const double* rest, AffineMap& am);
+// members/mkeys: from group_members (every label must have members)
+void affine_classify(agc_context* c, int32_t n, const int32_t* map, const uint32_t* members,
+                     const uint32_t* mkeys, int32_t n_c, int32_t threshold, const double* rest,
+                     AffineMap& am);
 // v_flat = P^T v (members/mkeys from group_members)
 void affine_restrict(agc_context* c, int32_t n, const AffineMap& am, const uint32_t* members,
                      const uint32_t* mkeys, const double* v, double* v_flat);

@@ -1,7 +1,7 @@
 // Deterministic segmented sum over sorted keys (internal).
 //
 // Items are processed in tiles of kWG (one per thread).  Inside a tile a
-// wave64 segmented scan (shuffles) and a carry across the four waves (LDS)
+// wave64 segmented scan (DPP lane moves) and a carry across the four waves (LDS)
 // give every run its partial sum.  A run whose segment starts inside the tile
 // writes its partial to the output; a run that continues a segment started in
 // an earlier tile writes its partial to carry[tile].  A second kernel adds,
@@ -52,16 +52,9 @@ __global__ __launch_bounds__(kWG) void k_seg_reduce(const K* __restrict__ keys, 
 #pragma unroll
     for (int i = 0; i < W; ++i) v[i] = (Acc)0;
   }
-  // wave-level segmented inclusive scan
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int64_t su = __shfl_up(seg, d);
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-      const Acc vu = __shfl_up(v[i], d);
-      if (lane >= (unsigned)d && su == seg) v[i] += vu;
-    }
-  }
+  // wave-level segmented inclusive scan (DPP lane moves; every lane is active
+  // here).  Within a tile a segment's index minus the tile's base fits in 32 bits.
+  wave_seg_scan<W>(valid ? (int32_t)(seg - base) : INT32_MAX, v);
   const int64_t seg0 = __shfl(seg, 0);
   if (lane == kWave - 1) {
     tail_seg[wave] = seg;
