@@ -262,6 +262,8 @@ __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G
   return t;
 }
 
+constexpr int kCarryBatch = 16;
+
 // q[r] for a row whose blocks may span several tiles.
 __device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const double* __restrict__ y,
                                            const double* __restrict__ carry, int64_t r, double q[3]) {
@@ -272,11 +274,24 @@ __device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const
   if (re <= rs) {
     q[0] = q[1] = q[2] = 0.0;
   } else if (w0 != w1) {
+    // a row across tiles (a hub row spans dozens): the carries are loaded
+    // kCarryBatch at a time and added in tile order
 #pragma unroll
     for (int i = 0; i < 3; ++i) q[i] = carry[(w0 * 2 + 1) * 3 + i];
-    for (int64_t w = w0 + 1; w <= w1; ++w) {
+    for (int64_t w = w0 + 1; w <= w1; w += kCarryBatch) {
+      double h[kCarryBatch][3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) q[i] += carry[(w * 2 + 0) * 3 + i];
+      for (int u = 0; u < kCarryBatch; ++u) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) h[u][i] = w + u <= w1 ? carry[((w + u) * 2 + 0) * 3 + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kCarryBatch; ++u) {
+        if (w + u <= w1) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) q[i] += h[u][i];
+        }
+      }
     }
   }
 }
@@ -395,16 +410,21 @@ __global__ __launch_bounds__(kWG) void k_jacobi(const int32_t* __restrict__ diag
 
 // ------------------------------------------------------------------ PCG
 
+// This thread's share of the fixed-order sum of part[0..G): elements
+// threadIdx.x, threadIdx.x + kWG, ...  (the loads are issued together).
+__device__ __forceinline__ double part_sum(const double* __restrict__ part, unsigned G) {
+  double s = 0.0;
+#pragma unroll 4
+  for (unsigned i = threadIdx.x; i < G; i += kWG) s += part[i];
+  return s;
+}
+
 // Sums K rows of per-workgroup partials part[k][0..G) in a fixed order and
 // gives every thread the totals (one barrier; lds holds K * kWaves doubles).
 template <int K>
 __device__ __forceinline__ void all_sum(const double* __restrict__ part, unsigned G, double* lds, double (&tot)[K]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double s = 0.0;
-    for (unsigned i = threadIdx.x; i < G; i += kWG) s += part[(int64_t)k * G + i];
-    tot[k] = s;
-  }
+  for (int k = 0; k < K; ++k) tot[k] = part_sum(part + (int64_t)k * G, G);
   wg_sum_all<K>(tot, lds);
 }
 
@@ -417,12 +437,10 @@ __device__ __forceinline__ int stop_code(int64_t j, double rz, double rr, double
   return 0;
 }
 
-// The stop test of iteration j from the update partials pb = [3][gb]
+// The stop test of iteration j on the totals t of the update partials
 // (gamma_j, r_j^T r_j, b^T b at j = 0); block 0 records the scalars.  Every
-// workgroup computes the same.  t receives the three totals.
-__device__ __forceinline__ int stop_scalars(int64_t j, const double* pb, unsigned gb, PcgState* st, double rtol,
-                                            double* lds, double (&t)[3]) {
-  all_sum<3>(pb, gb, lds, t);
+// workgroup computes the same.
+__device__ __forceinline__ int stop_scalars(int64_t j, const double* t, PcgState* st, double rtol) {
   double tol2;
   if (j == 0) {
     tol2 = rtol * rtol * t[2];
@@ -523,7 +541,7 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
                                                     const double* __restrict__ pa, unsigned ga,
                                                     const double* __restrict__ pb_in, double* __restrict__ pb_out,
                                                     PcgState* st, double rtol) {
-  __shared__ double lds_a[3 * kWaves], lds_b[kWaves], lds_c[2 * kWaves];
+  __shared__ double lds_a[4 * kWaves], lds_c[2 * kWaves];
   if (st->done) return;
   const int64_t blk = xcd_block();
   const int64_t i = blk * kWG + threadIdx.x;
@@ -545,16 +563,18 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
     }
     load_dinv(dinv, n, i, m);
   }
-  double t[3];
-  const int done = stop_scalars(j, pb_in, G, st, rtol, lds_a, t);
-  if (done) return;
-  double dl[1];
-  all_sum<1>(pa, ga, lds_b, dl);
+  // gamma_j, r_j^T r_j, b^T b (j = 0) and delta_j, in one reduction
+  double t[4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t[k] = part_sum(pb_in + (int64_t)k * G, G);
+  t[3] = part_sum(pa, ga);
+  wg_sum_all<4>(t, lds_a);
+  if (stop_scalars(j, t, st, rtol)) return;
   const double gamma = t[0];
-  double beta = 0.0, den = dl[0];
+  double beta = 0.0, den = t[3];
   if (j > 0) {
     beta = gamma / st->rz_hist[(j - 1) & 1];
-    den = dl[0] - beta * gamma / st->alpha_hist[(j - 1) & 1];
+    den = t[3] - beta * gamma / st->alpha_hist[(j - 1) & 1];
   }
   if (!(den > 0.0)) {   // p^T A p <= 0 or NaN: not SPD (every workgroup sees the same value)
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
@@ -601,7 +621,8 @@ __global__ __launch_bounds__(kWG) void k_pcg_check(int64_t j, const double* __re
   __shared__ double lds[3 * kWaves];
   if (st->done) return;
   double t[3];
-  (void)stop_scalars(j, pb, gb, st, rtol, lds, t);
+  all_sum<3>(pb, gb, lds, t);
+  (void)stop_scalars(j, t, st, rtol);
 }
 
 constexpr int kFirstChunk = 16;
@@ -650,9 +671,11 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
 
   // The host enqueues iterations in chunks and reads the device scalars (and
   // the block-Jacobi error word) in between.  After the first chunk, the
-  // chunk length is the number of iterations the residual's observed
-  // geometric decay still needs, with a margin: launches after convergence
-  // cost a flag read, a host round trip costs far more.
+  // chunk length is the number of iterations the residual's decay over the
+  // last chunk still needs, with a margin, but at most half the number
+  // already run: CG speeds up as it goes, so an early rate overestimates, and a
+  // launch after convergence, though it only reads a flag, still costs the
+  // host's enqueue time.
   int64_t launched = 0;
   int chunk = kFirstChunk;
   int prev_it = 0;
@@ -688,7 +711,9 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
       const double rate = log(hs->rr / prev_rr) / (double)(hs->iter - prev_it);
       want = 1.25 * log(hs->tol2 / hs->rr) / rate + 2.0;
     }
-    chunk = want < 4.0 ? 4 : (want > kMaxChunk ? kMaxChunk : (int)ceil(want));
+    const int64_t half = launched / 2;
+    const int cap = half < kFirstChunk ? kFirstChunk : (half > kMaxChunk ? kMaxChunk : (int)half);
+    chunk = want < 4.0 ? 4 : (want > cap ? cap : (int)ceil(want));
     prev_it = hs->iter;
     prev_rr = hs->rr;
   }
