@@ -276,8 +276,9 @@ void mesh_build(agc_context* c, Mesh& m, int32_t n, int64_t ne, const int32_t* e
 
   // full fine pattern (static)
   m.ff_row_ptr.ensure(sizeof(int32_t) * (n + 1));
-  m.ff_col.ensure(sizeof(int32_t) * 2 * m.nf);
-  m.ff_rowidx.ensure(sizeof(int32_t) * 2 * m.nf);
+  // padded as Matrix::reserve pads its pattern: the SpMV loads four blocks whole
+  m.ff_col.ensure(sizeof(int32_t) * (size_t)(plane_stride(2 * m.nf) + 4));
+  m.ff_rowidx.ensure(sizeof(int32_t) * (size_t)(plane_stride(2 * m.nf) + 4));
   m.ff_src.ensure(sizeof(uint32_t) * 2 * m.nf);
   m.ff_diag.ensure(sizeof(int32_t) * (n + 1));
   FullPattern fp{(int32_t*)m.ff_row_ptr.p, (int32_t*)m.ff_col.p, (int32_t*)m.ff_rowidx.p,

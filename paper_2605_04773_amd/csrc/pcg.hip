@@ -90,45 +90,67 @@ using GatherX = Gather<double>;
 // ------------------------------------------------------------- SpMV core
 
 // A thread's four blocks, loaded before anything that needs a scalar from
-// the previous kernel.  Blocks past nnzb carry row INT32_MAX and zeros.
+// the previous kernel.  Blocks past nnzb carry row INT32_MAX and column 0.
 template <class T>
 struct Quad {
   int32_t r[kItems], c[kItems];
   T a[9][kItems];
   int32_t next_row;   // row of the block after the thread's last one; INT32_MAX at the tile end
-  int32_t edge[4];    // thread 0: ri[t0 - 1], ri[t0], ri[t1 - 1], ri[t1] (-1 where absent)
+  int32_t edge[4];    // ri[t0 - 1], ri[t0], ri[t1 - 1], ri[t1] (-1 where absent); the same in every thread
 };
+
+// A thread's rows and columns (and the tile's edge rows)...  The pattern
+// arrays hold at least plane_stride(nnzb) + 4 entries and the values nine
+// planes of plane_stride(nnzb) plus 4 spare entries per plane, so the four
+// blocks from any k0 < nnzb can be loaded whole; a thread past
+// the end loads block 0, and blocks at or past nnzb are masked (row
+// INT32_MAX, column 0; their values are whatever the padding holds, and the
+// SpMV zeroes their products).  No load sits under a branch, so the wait for
+// the indices is the only one before the gathers are issued.
+template <class T>
+__device__ __forceinline__ void load_quad_index(int64_t w, const int32_t* __restrict__ ri,
+                                                const int32_t* __restrict__ col, int64_t nnzb, Quad<T>& q) {
+  const int64_t t0 = w * kTile;
+  const int64_t t1 = (t0 + kTile < nnzb) ? t0 + kTile : nnzb;
+  const int64_t k0 = t0 + (int64_t)threadIdx.x * kItems;
+  const int64_t kl = k0 < nnzb ? k0 : 0;
+  int32_t r4[kItems], c4[kItems];
+  load4(ri + kl, r4);
+  load4(col + kl, c4);
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const bool in = k0 + j < nnzb;
+    q.r[j] = in ? r4[j] : INT32_MAX;
+    q.c[j] = in ? c4[j] : 0;
+  }
+  const int64_t kn = k0 + kItems;
+  const int32_t nr = ri[kn < t1 ? kn : t0];
+  q.next_row = kn < t1 ? nr : INT32_MAX;
+  // uniform across the workgroup
+  const int32_t before = ri[t0 > 0 ? t0 - 1 : 0], after = ri[t1 < nnzb ? t1 : t1 - 1];
+  q.edge[0] = t0 > 0 ? before : -1;
+  q.edge[1] = ri[t0];
+  q.edge[2] = ri[t1 - 1];
+  q.edge[3] = t1 < nnzb ? after : -1;
+}
+
+// ...and its nine value planes.
+template <class T>
+__device__ __forceinline__ void load_quad_vals(int64_t w, const T* __restrict__ vals, int64_t nnzb, int64_t stride,
+                                               Quad<T>& q) {
+  const int64_t k0 = w * kTile + (int64_t)threadIdx.x * kItems;
+  const int64_t kl = k0 < nnzb ? k0 : 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) load4(vals + (int64_t)i * stride + kl, q.a[i]);
+  // the loads above are issued before the gathers that follow
+  __builtin_amdgcn_sched_barrier(0);
+}
 
 template <class T>
 __device__ __forceinline__ void load_quad(int64_t w, const int32_t* __restrict__ ri, const int32_t* __restrict__ col,
                                           const T* __restrict__ vals, int64_t nnzb, int64_t stride, Quad<T>& q) {
-  const int64_t t0 = w * kTile;
-  const int64_t t1 = (t0 + kTile < nnzb) ? t0 + kTile : nnzb;
-  const int64_t k0 = t0 + (int64_t)threadIdx.x * kItems;
-  if (k0 + kItems <= nnzb) {
-    load4(ri + k0, q.r);
-    load4(col + k0, q.c);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) load4(vals + (int64_t)i * stride + k0, q.a[i]);
-  } else {
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int64_t k = k0 + j;
-      const bool in = k < nnzb;
-      q.r[j] = in ? ri[k] : INT32_MAX;
-      q.c[j] = in ? col[k] : 0;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) q.a[i][j] = in ? vals[(int64_t)i * stride + k] : (T)0;
-    }
-  }
-  const int64_t kn = k0 + kItems;
-  q.next_row = (kn < t1) ? ri[kn] : INT32_MAX;
-  if (threadIdx.x == 0) {
-    q.edge[0] = t0 > 0 ? ri[t0 - 1] : -1;
-    q.edge[1] = ri[t0];
-    q.edge[2] = ri[t1 - 1];
-    q.edge[3] = t1 < nnzb ? ri[t1] : -1;
-  }
+  load_quad_index(w, ri, col, nnzb, q);
+  load_quad_vals(w, vals, nnzb, stride, q);
 }
 
 struct TileLds {
@@ -153,17 +175,28 @@ __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G
   double v[kItems][3];
   double dot = 0.0;
   double pr0[3] = {0.0, 0.0, 0.0}, pr3[3] = {0.0, 0.0, 0.0};
-  if (DOT) {
-    if (q.r[0] != INT32_MAX) g.get(q.r[0], pr0);
-    if (q.r[kItems - 1] != q.r[0] && q.r[kItems - 1] != INT32_MAX) g.get(q.r[kItems - 1], pr3);
+  if (DOT) {   // gathered unconditionally (a masked row reads entry 0), with the columns
+    const int32_t r0 = q.r[0] != INT32_MAX ? q.r[0] : 0;
+    const int32_t r3 = q.r[kItems - 1] != INT32_MAX ? q.r[kItems - 1] : r0;
+    g.get(r0, pr0);
+    g.get(r3, pr3);
   }
+  double xg[kItems][3];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) g.get(q.c[j], xg[j]);
+  // all gathers are in flight before any product is formed: left to itself
+  // the scheduler interleaves them with the arithmetic, one round trip each
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    double xv[3];
-    g.get(q.c[j], xv);
-    v[j][0] = (double)q.a[0][j] * xv[0] + (double)q.a[1][j] * xv[1] + (double)q.a[2][j] * xv[2];
-    v[j][1] = (double)q.a[3][j] * xv[0] + (double)q.a[4][j] * xv[1] + (double)q.a[5][j] * xv[2];
-    v[j][2] = (double)q.a[6][j] * xv[0] + (double)q.a[7][j] * xv[1] + (double)q.a[8][j] * xv[2];
+    const double* xv = xg[j];
+    const bool in = q.r[j] != INT32_MAX;   // a masked block's values may be padding
+    const double v0 = (double)q.a[0][j] * xv[0] + (double)q.a[1][j] * xv[1] + (double)q.a[2][j] * xv[2];
+    const double v1 = (double)q.a[3][j] * xv[0] + (double)q.a[4][j] * xv[1] + (double)q.a[5][j] * xv[2];
+    const double v2 = (double)q.a[6][j] * xv[0] + (double)q.a[7][j] * xv[1] + (double)q.a[8][j] * xv[2];
+    v[j][0] = in ? v0 : 0.0;
+    v[j][1] = in ? v1 : 0.0;
+    v[j][2] = in ? v2 : 0.0;
   }
   if (DOT) {
 #pragma unroll
@@ -264,18 +297,15 @@ __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G
 
 constexpr int kCarryBatch = 16;
 
-// q[r] for a row whose blocks may span several tiles.
-__device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const double* __restrict__ y,
-                                           const double* __restrict__ carry, int64_t r, double q[3]) {
-#pragma unroll
-  for (int i = 0; i < 3; ++i) q[i] = y[3 * r + i];   // issued with the row pointers; used unless split
-  const int64_t rs = rp[r], re = rp[r + 1];
+// q = y[r] corrected for a row whose blocks may span several tiles (rs, re:
+// its block range): then q is the last partial of its first tile plus the
+// first partials of the later ones, added in tile order.
+__device__ __forceinline__ void row_fix(int64_t rs, int64_t re, const double* __restrict__ carry, double q[3]) {
   const int64_t w0 = rs / kTile, w1 = (re - 1) / kTile;
   if (re <= rs) {
     q[0] = q[1] = q[2] = 0.0;
   } else if (w0 != w1) {
-    // a row across tiles (a hub row spans dozens): the carries are loaded
-    // kCarryBatch at a time and added in tile order
+    // a hub row spans dozens of tiles: the carries are loaded kCarryBatch at a time
 #pragma unroll
     for (int i = 0; i < 3; ++i) q[i] = carry[(w0 * 2 + 1) * 3 + i];
     for (int64_t w = w0 + 1; w <= w1; w += kCarryBatch) {
@@ -294,6 +324,14 @@ __device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const
       }
     }
   }
+}
+
+// q[r] for a row whose blocks may span several tiles.
+__device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const double* __restrict__ y,
+                                           const double* __restrict__ carry, int64_t r, double q[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q[i] = y[3 * r + i];   // issued with the row pointers; used unless split
+  row_fix(rp[r], rp[r + 1], carry, q);
 }
 
 template <class T>
@@ -410,21 +448,53 @@ __global__ __launch_bounds__(kWG) void k_jacobi(const int32_t* __restrict__ diag
 
 // ------------------------------------------------------------------ PCG
 
-// This thread's share of the fixed-order sum of part[0..G): elements
-// threadIdx.x, threadIdx.x + kWG, ...  (the loads are issued together).
-__device__ __forceinline__ double part_sum(const double* __restrict__ part, unsigned G) {
+// Per-workgroup partials are stored in rows of part_stride(G) doubles (G
+// rounded up to even), so that a row can be read with 16-byte loads: lane t
+// of batch m reads entries 2 (m kWG + t) and the one after.  part_sum is this
+// thread's share of the fixed-order sum of a row; part_load issues the first
+// kPartBatch loads in one go, so that a kernel can issue them before its
+// other loads and add them (part_finish) while those are in flight.  A lane
+// past the end reads a valid pair elsewhere in the row (rather than every
+// such lane hitting entry 0) and masks it.
+constexpr int kPartBatch = 2;
+__host__ __device__ inline int64_t part_stride(int64_t G) { return (G + 1) & ~(int64_t)1; }
+__device__ __forceinline__ void part_load(const double* __restrict__ part, unsigned G, vd2 (&v)[kPartBatch]) {
+#pragma unroll
+  for (int m = 0; m < kPartBatch; ++m) {
+    const unsigned e = 2 * (m * kWG + threadIdx.x);
+    const unsigned ec = e < G ? e : (e % G) & ~1u;
+    const vd2 q = *reinterpret_cast<const vd2*>(part + ec);
+    v[m].x = e < G ? q.x : 0.0;
+    v[m].y = e + 1 < G ? q.y : 0.0;
+  }
+}
+__device__ __forceinline__ double part_finish(const double* __restrict__ part, unsigned G,
+                                              const vd2 (&v)[kPartBatch]) {
   double s = 0.0;
-#pragma unroll 4
-  for (unsigned i = threadIdx.x; i < G; i += kWG) s += part[i];
+#pragma unroll
+  for (int m = 0; m < kPartBatch; ++m) {
+    s += v[m].x;
+    s += v[m].y;
+  }
+  for (unsigned e = 2 * (kPartBatch * kWG + threadIdx.x); e < G; e += 2 * kWG) {
+    s += part[e];
+    if (e + 1 < G) s += part[e + 1];
+  }
   return s;
 }
+__device__ __forceinline__ double part_sum(const double* __restrict__ part, unsigned G) {
+  vd2 v[kPartBatch];
+  part_load(part, G, v);
+  return part_finish(part, G, v);
+}
 
-// Sums K rows of per-workgroup partials part[k][0..G) in a fixed order and
-// gives every thread the totals (one barrier; lds holds K * kWaves doubles).
+// Sums K rows of per-workgroup partials part[k][0..G) (row stride
+// part_stride(G)) in a fixed order and gives every thread the totals (one
+// barrier; lds holds K * kWaves doubles).
 template <int K>
 __device__ __forceinline__ void all_sum(const double* __restrict__ part, unsigned G, double* lds, double (&tot)[K]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) tot[k] = part_sum(part + (int64_t)k * G, G);
+  for (int k = 0; k < K; ++k) tot[k] = part_sum(part + (int64_t)k * part_stride(G), G);
   wg_sum_all<K>(tot, lds);
 }
 
@@ -437,10 +507,28 @@ __device__ __forceinline__ int stop_code(int64_t j, double rz, double rr, double
   return 0;
 }
 
+// The scalars an iteration reads from the device state, read together when
+// a kernel starts: read after a barrier, they would add a round trip to the
+// kernel's critical path.
+struct StateIn {
+  int32_t done, max_iter;
+  double tol2, rz_prev, alpha_prev;   // the last two: of iteration j - 1 (unused at j = 0)
+};
+__device__ __forceinline__ StateIn read_state(const PcgState* st, int64_t j) {
+  StateIn s;
+  s.done = st->done;
+  s.max_iter = st->max_iter;
+  s.tol2 = st->tol2;
+  s.rz_prev = st->rz_hist[(j - 1) & 1];
+  s.alpha_prev = st->alpha_hist[(j - 1) & 1];
+  return s;
+}
+
 // The stop test of iteration j on the totals t of the update partials
 // (gamma_j, r_j^T r_j, b^T b at j = 0); block 0 records the scalars.  Every
 // workgroup computes the same.
-__device__ __forceinline__ int stop_scalars(int64_t j, const double* t, PcgState* st, double rtol) {
+__device__ __forceinline__ int stop_scalars(int64_t j, const double* t, PcgState* st, const StateIn& in,
+                                            double rtol) {
   double tol2;
   if (j == 0) {
     tol2 = rtol * rtol * t[2];
@@ -449,9 +537,9 @@ __device__ __forceinline__ int stop_scalars(int64_t j, const double* t, PcgState
       st->tol2 = tol2;
     }
   } else {
-    tol2 = st->tol2;
+    tol2 = in.tol2;
   }
-  const int done = stop_code(j, t[0], t[1], t[2], tol2, st->max_iter);
+  const int done = stop_code(j, t[0], t[1], t[2], tol2, in.max_iter);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->iter = (int32_t)j;
     st->rr = t[1];
@@ -507,9 +595,10 @@ __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, 
   wg_sum_all<3>(t, lds);
   const unsigned G = gridDim.x;
   if (threadIdx.x == 0) {
+    const int64_t gs = part_stride(G);
     pb[blockIdx.x] = t[0];
-    pb[G + blockIdx.x] = t[1];
-    pb[2 * G + blockIdx.x] = t[2];
+    pb[gs + blockIdx.x] = t[1];
+    pb[2 * gs + blockIdx.x] = t[2];
   }
 }
 
@@ -521,10 +610,14 @@ __global__ __launch_bounds__(kWG) void k_pcg_spmv(const int32_t* __restrict__ co
                                                   double* __restrict__ carry, double* __restrict__ pa,
                                                   const PcgState* st) {
   __shared__ TileLds L;
-  if (st->done) return;   // before the loads: a wave cannot retire with loads in flight
   const int64_t t = xcd_block();
   Quad<T> q;
-  load_quad(t, ri, col, vals, nnzb, stride, q);
+  // The flag is read with the index loads, before the value planes: a launch
+  // after convergence then reads only the indices, and a working one does
+  // not wait for the flag before it starts loading.
+  load_quad_index(t, ri, col, nnzb, q);
+  if (st->done) return;
+  load_quad_vals(t, vals, nnzb, stride, q);
   const double d = spmv_tile<T, Gather<T>, true>(t, q, Gather<T>{z}, w, carry, L);
   if (threadIdx.x == 0) pa[t] = d;
 }
@@ -542,39 +635,46 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
                                                     const double* __restrict__ pb_in, double* __restrict__ pb_out,
                                                     PcgState* st, double rtol) {
   __shared__ double lds_a[4 * kWaves], lds_c[2 * kWaves];
-  if (st->done) return;
   const int64_t blk = xcd_block();
   const int64_t i = blk * kWG + threadIdx.x;
   const bool in = i < n;
+  const int64_t ic = in ? i : (int64_t)n - 1;   // threads past the end load the last row and store nothing
   const unsigned G = gridDim.x;
-  // everything but the scalars is loaded before the reductions
-  double wv[3] = {0.0, 0.0, 0.0}, pv[3] = {0.0, 0.0, 0.0}, sw[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0};
-  double rv[3] = {0.0, 0.0, 0.0}, zv[3] = {0.0, 0.0, 0.0};
-  double m[6];
-  if (in) {
-    row_result(rp, wy, carry, i, wv);
+  const StateIn in_state = read_state(st, j);
+  // Issue order: the partials of the scalars (in L2), then the row's vectors
+  // (one row per thread, no branch), then the sum of the partials, which
+  // waits for the partials alone; the vectors arrive meanwhile.
+  const int64_t GS = part_stride(G);
+  vd2 part[4][kPartBatch];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      pv[k] = p[3 * i + k];
-      sw[k] = sv[3 * i + k];
-      xv[k] = x[3 * i + k];
-      rv[k] = r[3 * i + k];
-      zv[k] = (double)z[3 * i + k];
-    }
-    load_dinv(dinv, n, i, m);
+  for (int k = 0; k < 3; ++k) part_load(pb_in + k * GS, G, part[k]);
+  part_load(pa, ga, part[3]);
+  const int64_t rs = rp[ic], re = rp[ic + 1];
+  double wv[3], pv[3], sw[3], xv[3], rv[3], zv[3], m[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    wv[k] = wy[3 * ic + k];
+    pv[k] = p[3 * ic + k];
+    sw[k] = sv[3 * ic + k];
+    xv[k] = x[3 * ic + k];
+    rv[k] = r[3 * ic + k];
+    zv[k] = (double)z[3 * ic + k];
   }
+  load_dinv(dinv, n, ic, m);
+  if (in_state.done) return;
   // gamma_j, r_j^T r_j, b^T b (j = 0) and delta_j, in one reduction
   double t[4];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) t[k] = part_sum(pb_in + (int64_t)k * G, G);
-  t[3] = part_sum(pa, ga);
+  for (int k = 0; k < 3; ++k) t[k] = part_finish(pb_in + k * GS, G, part[k]);
+  t[3] = part_finish(pa, ga, part[3]);
   wg_sum_all<4>(t, lds_a);
-  if (stop_scalars(j, t, st, rtol)) return;
+  if (stop_scalars(j, t, st, in_state, rtol)) return;
+  if (in) row_fix(rs, re, carry, wv);
   const double gamma = t[0];
   double beta = 0.0, den = t[3];
   if (j > 0) {
-    beta = gamma / st->rz_hist[(j - 1) & 1];
-    den = t[3] - beta * gamma / st->alpha_hist[(j - 1) & 1];
+    beta = gamma / in_state.rz_prev;
+    den = t[3] - beta * gamma / in_state.alpha_prev;
   }
   if (!(den > 0.0)) {   // p^T A p <= 0 or NaN: not SPD (every workgroup sees the same value)
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 3;
@@ -610,8 +710,8 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
   wg_sum_all<2>(u, lds_c);
   if (threadIdx.x == 0) {
     pb_out[blk] = u[0];
-    pb_out[G + blk] = u[1];
-    pb_out[2 * G + blk] = 0.0;
+    pb_out[GS + blk] = u[1];
+    pb_out[2 * GS + blk] = 0.0;
   }
 }
 
@@ -619,10 +719,11 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
 __global__ __launch_bounds__(kWG) void k_pcg_check(int64_t j, const double* __restrict__ pb, unsigned gb,
                                                    PcgState* st, double rtol) {
   __shared__ double lds[3 * kWaves];
-  if (st->done) return;
+  const StateIn in_state = read_state(st, j);
+  if (in_state.done) return;
   double t[3];
   all_sum<3>(pb, gb, lds, t);
-  (void)stop_scalars(j, t, st, rtol);
+  (void)stop_scalars(j, t, st, in_state, rtol);
 }
 
 constexpr int kFirstChunk = 16;
@@ -645,8 +746,9 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   const unsigned gr = blocks_for(n, kWG);
   const unsigned gs = blocks_for(a.nnzb, kTile);
   // update partials, double-buffered by parity of j: iteration j reads pbs[j%2]
-  double* pbs[2] = {c->ws.get<double>("pcg.pb0", 3 * (int64_t)gr), c->ws.get<double>("pcg.pb1", 3 * (int64_t)gr)};
-  double* pa = c->ws.get<double>("pcg.pa", gs);
+  double* pbs[2] = {c->ws.get<double>("pcg.pb0", 3 * part_stride(gr)),
+                    c->ws.get<double>("pcg.pb1", 3 * part_stride(gr))};
+  double* pa = c->ws.get<double>("pcg.pa", part_stride(gs));
   double* carry = spmv_carry(c, a);
   PcgState* st = (PcgState*)c->d_pcg;
   PcgState* hs = (PcgState*)c->h_pcg;
