@@ -105,6 +105,87 @@ def cpu_baseline(p, rtol):
                       f"numpy/scipy single-threaded"}
 
 
+N_DRIFT_SYSTEMS = 10
+
+
+def drift_systems(args, p, ctx, prob, tags, x, mp, setup_ms, torch, agc, synth):
+    """A sequence of systems on one mesh whose tags drift (about 10% flip per
+    system): every solve re-aggregates, re-assembles, solves and prolongates.
+    Reported: per-system ms of the mixed solve (the value is their median), the
+    flip fractions, coarse sizes, GB/s of the assembly and of the PCG SpMV, and
+    the fine FP64 comparator (the same for every system: it does not use tags)."""
+    mixed_kw = dict(rtol=args.rtol, precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol)
+    steps = max(1, min(args.steps, 5))
+
+    def solve(**kw):
+        return agc.agc_solve(ctx, prob, agc.make_opts(**kw), x, mp)
+
+    def rel(ref):
+        return float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
+
+    n_e, n_v = int(p["elem_verts"].shape[0]), int(p["n_verts"])
+    systems, prev, ti = [], None, None
+    for it in range(N_DRIFT_SYSTEMS):
+        tg = synth.drift_tags(p, it)
+        flip = None if prev is None else round(float(np.mean(tg != prev)), 4)
+        prev = tg
+        tags.copy_(torch.from_numpy(tg))
+        torch.cuda.synchronize()
+        solve(rtol=1e-12, max_iter=50000)
+        ref = x.clone()
+        ms, info = time_steps(lambda: solve(**mixed_kw), steps, 1, torch)
+        err = rel(ref)
+        ph = solve(timing=1, **mixed_kw)
+        asm_bytes = n_e * (16 + 144 * 8) + n_v * (24 + 4) + int(info.nnzb) * (9 * 8 + 4)
+        systems.append({"system": it, "ms": round(ms, 3), "flip_fraction": flip, "n_coarse": info.n_coarse,
+                        "nnzb_coarse": int(info.nnzb), "pcg_iters": info.pcg_iters,
+                        "rel_err_vs_fp64": err,
+                        "phase_ms": {"aggregate": round(ph.ms_aggregate, 3), "assemble": round(ph.ms_assemble, 3),
+                                     "pcg": round(ph.ms_pcg, 3), "prolong": round(ph.ms_prolong, 3)},
+                        "assembly_gbs": round(asm_bytes / (ph.ms_assemble * 1e-3) / 1e9, 1)})
+        log(f"[bench] system {it}: {ms:.2f} ms, flips {flip}, n_c={info.n_coarse} nnzb={info.nnzb} "
+            f"pcg_iters={info.pcg_iters} err={err:.2e}")
+        if it == 0:
+            ti = solve(timing=2, **mixed_kw)
+    spmv_avg_ms = ti.ms_spmv / max(ti.spmv_launches, 1)
+    spmv_alg = spmv_bytes(ti.nnzb, ti.n_coarse, 4)
+    achieved = spmv_alg / (spmv_avg_ms * 1e-3) / 1e9
+    solve(rtol=1e-12, max_iter=50000, coarsen=0)
+    ref_f = x.clone()
+    ms_fine, finfo = time_steps(lambda: solve(rtol=args.rtol_fine, coarsen=0), steps, 1, torch)
+    err_f = rel(ref_f)
+    fi = solve(rtol=args.rtol_fine, coarsen=0, timing=2)
+    log(f"[bench] fine FP64 comparator: {ms_fine:.2f} ms, pcg_iters={finfo.pcg_iters} err={err_f:.2e}")
+    per = sorted(sy["ms"] for sy in systems)
+    med = per[len(per) // 2]
+    return {
+        "metric": "ms per Newton linear solve (coarsen+assemble+PCG+prolong) vs fine PCG, 1 GPU",
+        "value": med, "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": med,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 SpMV values + f64 assembly sums, vectors, dots, residuals", "data": "synthetic",
+        "config": {
+            "workload": (f"{args.config}: cube grid, 5 tets/cube, {n_v} vertices, {n_e} tets, {p['frac']:.0%} "
+                         f"collapsible edges, {N_DRIFT_SYSTEMS} systems with drifting tags, mixed precision, "
+                         f"rtol {args.rtol:g}; value = median over the systems"),
+            "n_verts": n_v, "n_elems": n_e, "mesh_setup_ms": round(setup_ms, 2), "rtol": args.rtol,
+        },
+        "roofline": {
+            "kernel": "k_pcg_spmv<float> (fused SpMV w = A z and z^T w, float32 matrix), system 0",
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(spmv_avg_ms * 1e3, 3), "launches": ti.spmv_launches,
+            "algorithmic_bytes_per_launch": int(spmv_alg),
+        },
+        "systems": systems,
+        "fine_fp64_ms_per_solve": round(ms_fine, 3), "fine_pcg_iters": finfo.pcg_iters, "fine_rel_err": err_f,
+        "rtol_fine": args.rtol_fine,
+        "speedup_vs_fine_fp64": round(ms_fine / med, 3),
+        "fine_spmv_us": round(fi.ms_spmv / max(fi.spmv_launches, 1) * 1e3, 3),
+        "fine_spmv_gbs": round(spmv_bytes(fi.nnzb, fi.n_coarse, 8) /
+                               (fi.ms_spmv / max(fi.spmv_launches, 1) * 1e-3) / 1e9, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,7 +224,7 @@ def main():
 
     log(f"[bench] generating {args.config}")
     t0 = time.perf_counter()
-    p = synth.make_config(args.config)
+    p = synth.make_config(args.config, log=lambda m: log(f"[bench]   {m} ({time.perf_counter() - t0:.0f}s)"))
     log(f"[bench] generated in {time.perf_counter() - t0:.1f}s: {p['n_verts']} vertices, "
         f"{p['elem_verts'].shape[0]} elements, {p['edges'].shape[0]} edges")
     dev = torch.device("cuda", 0)
@@ -162,6 +243,13 @@ def main():
     prob = agc.make_problem(mesh, edges, tags, eh, g, t(p["pos"], torch.float64))
     x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=dev)
     mp = torch.empty(p["n_verts"], dtype=torch.int32, device=dev)
+
+    if "drift_delta" in p:
+        out = drift_systems(args, p, ctx, prob, tags, x, mp, setup_ms, torch, agc, synth)
+        print(json.dumps(out), flush=True)
+        mesh.close()
+        ctx.close()
+        return
 
     def solver(rtol=args.rtol, **kw):
         o = agc.make_opts(rtol=rtol, **kw)

@@ -60,7 +60,11 @@ typedef struct agc_matrix agc_matrix;   /* assembled BSR 3x3 matrix, device resi
 /* ---------------------------------------------------------------- context */
 
 /* Creates a context on HIP device `device`, enqueuing on `stream` (a
- * hipStream_t; NULL = the legacy default stream).  *ctx receives the handle. */
+ * hipStream_t; NULL = the legacy default stream).  *ctx receives the handle.
+ * The environment variable AGC_PCG_REDUCE, read here, selects how the PCG
+ * sums its per-workgroup partials: unset (or any other value) = by system
+ * size, "0" = inside the update kernel always, "1" = in a separate reduction
+ * kernel always.  The two differ only in summation order. */
 agc_status agc_create(agc_context** ctx, int32_t device, void* stream);
 agc_status agc_set_stream(agc_context* ctx, void* stream);
 /* Frees the context's workspace.  Matrices and meshes must be destroyed first. */

@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <cstdlib>
+
 #include "internal.h"
 
 struct agc_mesh {
@@ -184,6 +186,10 @@ agc_status agc_create(agc_context** out, int32_t device, void* stream) {
   if (!c) return AGC_ERR_OUT_OF_MEMORY;
   c->device = device;
   c->stream = (hipStream_t)stream;
+  if (const char* e = std::getenv("AGC_PCG_REDUCE")) {
+    if (e[0] == '0' && e[1] == 0) c->pcg_reduce = 0;
+    if (e[0] == '1' && e[1] == 0) c->pcg_reduce = 1;
+  }
   try {
     int ndev = 0;
     AGC_HIP(hipGetDeviceCount(&ndev));

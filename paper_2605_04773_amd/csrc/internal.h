@@ -183,6 +183,10 @@ struct agc_context {
   bool kernel_timing = false;   // replay and time the PCG SpMV after each PCG solve
   double spmv_ms = 0.0;         // summed duration of the timed SpMV launches
   int64_t spmv_n = 0;
+  // PCG partial-sum reduction between the SpMV and the update: -1 when the
+  // system is large enough (the default), 0 never, 1 always; set at creation
+  // from the environment variable AGC_PCG_REDUCE ("0" or "1"), for testing
+  int pcg_reduce = -1;
   agc::Matrix solve_a;         // matrices reused across agc_solve calls
   agc::Matrix solve_a64;
   agc::Matrix solve_fine;      // the fine system for post-coarsening

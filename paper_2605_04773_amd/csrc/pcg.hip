@@ -622,9 +622,42 @@ __global__ __launch_bounds__(kWG) void k_pcg_spmv(const int32_t* __restrict__ co
   if (threadIdx.x == 0) pa[t] = d;
 }
 
+// Between K_1 and K_2 on large systems: every workgroup of K_2 sums all the
+// partials it reads, so their reading grows as (workgroups of K_2) x
+// (partials); past kReduceWork that is shrunk to kReduceSlices partials per
+// quantity here.  Workgroup q sums slice q of each of the four rows (the
+// three of pb, rows of G, and pa, ga long) in a fixed order and writes
+// red[k][q] (rows of part_stride(kReduceSlices)).
+constexpr int kReduceSlices = 64;
+constexpr int64_t kReduceWork = int64_t(1) << 23;   // doubles read per update, summed over its workgroups
+__global__ __launch_bounds__(kWG) void k_pcg_reduce(const double* __restrict__ pb, unsigned G,
+                                                    const double* __restrict__ pa, unsigned ga,
+                                                    double* __restrict__ red) {
+  __shared__ double lds[4 * kWaves];
+  const unsigned q = blockIdx.x;
+  double t[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* row = k < 3 ? pb + k * part_stride(G) : pa;
+    const unsigned len = k < 3 ? G : ga;
+    const unsigned lo = (unsigned)((uint64_t)len * q / kReduceSlices);
+    const unsigned hi = (unsigned)((uint64_t)len * (q + 1) / kReduceSlices);
+    double acc = 0.0;
+    for (unsigned e = lo + threadIdx.x; e < hi; e += kWG) acc += row[e];
+    t[k] = acc;
+  }
+  wg_sum_all<4>(t, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k * part_stride(kReduceSlices) + q] = t[k];
+  }
+}
+
 // K_2: the update of iteration j.  Reads the partials pb_in of gamma_j and
-// r_j^T r_j (and b^T b at j = 0) and pa of delta_j; writes those of j + 1 to
-// pb_out (a different buffer: every workgroup reads all of pb_in).
+// r_j^T r_j (and b^T b at j = 0), rows of gin, and pa of delta_j; writes
+// those of j + 1 to pb_out, rows of G = gridDim.x (a different buffer: every
+// workgroup reads all of pb_in).  On large systems pb_in and pa are the
+// rows of k_pcg_reduce.
 template <class Z>
 __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __restrict__ rp, int32_t n,
                                                     const double* __restrict__ wy, const double* __restrict__ carry,
@@ -632,7 +665,8 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
                                                     double* __restrict__ sv, double* __restrict__ x,
                                                     double* __restrict__ r, Z* __restrict__ z,
                                                     const double* __restrict__ pa, unsigned ga,
-                                                    const double* __restrict__ pb_in, double* __restrict__ pb_out,
+                                                    const double* __restrict__ pb_in, unsigned gin,
+                                                    double* __restrict__ pb_out,
                                                     PcgState* st, double rtol) {
   __shared__ double lds_a[4 * kWaves], lds_c[2 * kWaves];
   const int64_t blk = xcd_block();
@@ -644,10 +678,10 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
   // Issue order: the partials of the scalars (in L2), then the row's vectors
   // (one row per thread, no branch), then the sum of the partials, which
   // waits for the partials alone; the vectors arrive meanwhile.
-  const int64_t GS = part_stride(G);
+  const int64_t GS = part_stride(G), GIS = part_stride(gin);
   vd2 part[4][kPartBatch];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) part_load(pb_in + k * GS, G, part[k]);
+  for (int k = 0; k < 3; ++k) part_load(pb_in + k * GIS, gin, part[k]);
   part_load(pa, ga, part[3]);
   const int64_t rs = rp[ic], re = rp[ic + 1];
   double wv[3], pv[3], sw[3], xv[3], rv[3], zv[3], m[6];
@@ -665,7 +699,7 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
   // gamma_j, r_j^T r_j, b^T b (j = 0) and delta_j, in one reduction
   double t[4];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) t[k] = part_finish(pb_in + k * GS, G, part[k]);
+  for (int k = 0; k < 3; ++k) t[k] = part_finish(pb_in + k * GIS, gin, part[k]);
   t[3] = part_finish(pa, ga, part[3]);
   wg_sum_all<4>(t, lds_a);
   if (stop_scalars(j, t, st, in_state, rtol)) return;
@@ -749,6 +783,10 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   double* pbs[2] = {c->ws.get<double>("pcg.pb0", 3 * part_stride(gr)),
                     c->ws.get<double>("pcg.pb1", 3 * part_stride(gr))};
   double* pa = c->ws.get<double>("pcg.pa", part_stride(gs));
+  // the partials every update workgroup would read, summed over them
+  const int64_t upd_reads = (int64_t)gr * (3 * (int64_t)gr + gs);
+  const bool use_red = c->pcg_reduce < 0 ? upd_reads > kReduceWork : c->pcg_reduce == 1;
+  double* red = use_red ? c->ws.get<double>("pcg.red", 4 * part_stride(kReduceSlices)) : nullptr;
   double* carry = spmv_carry(c, a);
   PcgState* st = (PcgState*)c->d_pcg;
   PcgState* hs = (PcgState*)c->h_pcg;
@@ -785,17 +823,27 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   for (;;) {
     for (int it = 0; it < chunk; ++it) {
       const int64_t j = launched + it;
-      if (a.dtype == AGC_F64) {
+      if (a.dtype == AGC_F64)
         k_pcg_spmv<double><<<gs, kWG, 0, c->stream>>>(a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, a.stride,
                                                       (const double*)z, w, carry, pa, st);
-        k_pcg_update<double><<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, p, sv, x, r, (double*)z, pa,
-                                                        gs, pbs[j & 1], pbs[(j + 1) & 1], st, rtol);
-      } else {
+      else
         k_pcg_spmv<float><<<gs, kWG, 0, c->stream>>>(a.ci(), a.ri(), (const float*)a.vals.p, a.nnzb, a.stride,
                                                      (const float*)z, w, carry, pa, st);
-        k_pcg_update<float><<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, p, sv, x, r, (float*)z, pa,
-                                                       gs, pbs[j & 1], pbs[(j + 1) & 1], st, rtol);
+      const double* pb_in = pbs[j & 1];
+      const double* pa_in = pa;
+      unsigned gin = gr, ga = gs;
+      if (red) {
+        k_pcg_reduce<<<kReduceSlices, kWG, 0, c->stream>>>(pb_in, gr, pa, gs, red);
+        pb_in = red;
+        pa_in = red + 3 * part_stride(kReduceSlices);
+        gin = ga = kReduceSlices;
       }
+      if (a.dtype == AGC_F64)
+        k_pcg_update<double><<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, p, sv, x, r, (double*)z, pa_in,
+                                                        ga, pb_in, gin, pbs[(j + 1) & 1], st, rtol);
+      else
+        k_pcg_update<float><<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, p, sv, x, r, (float*)z, pa_in,
+                                                       ga, pb_in, gin, pbs[(j + 1) & 1], st, rtol);
     }
     launched += chunk;
     k_pcg_check<<<1, kWG, 0, c->stream>>>(launched, pbs[launched & 1], gr, st, rtol);

@@ -156,12 +156,16 @@ def random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
     return r
 
 
-def elastic_blocks(pos, tets, rot, mu, lam, rho, h, out=None, chunk=1 << 17):
-    """12x12 row-major element blocks (DoF order 3a+k): R K0 R^T + rho V/(4 h^2) I, symmetrised."""
+def elastic_blocks(pos, tets, rot, mu, lam, rho, h, out=None, chunk=1 << 17, progress=None):
+    """12x12 row-major element blocks (DoF order 3a+k): R K0 R^T + rho V/(4 h^2) I, symmetrised.
+
+    ``progress(done, total)`` is called after every 16 chunks, when given."""
     n = tets.shape[0]
     if out is None:
         out = np.empty((n, 144), dtype=np.float64)
-    for s in range(0, n, chunk):
+    for ci, s in enumerate(range(0, n, chunk)):
+        if progress is not None and ci % 16 == 0 and ci > 0:
+            progress(s, n)
         e = slice(s, min(n, s + chunk))
         vol, grads = shape_gradients(pos, tets[e])
         k0 = linear_stiffness(vol, grads, mu, lam)                     # (m,4,4,3,3)
@@ -217,14 +221,20 @@ def edge_tags(field, pos, edges, frac, shift=None):
 # --------------------------------------------------------------------------
 
 def grid_problem(n: int, seed: int, frac: float, young: float = YOUNG, poisson: float = POISSON,
-                 rho: float = DENSITY, h: float = H_STEP) -> dict:
-    """Unit cube as an n^3 grid of cubes, 5 tets each, co-rotated stiffness + lumped mass."""
+                 rho: float = DENSITY, h: float = H_STEP, log=None) -> dict:
+    """Unit cube as an n^3 grid of cubes, 5 tets each, co-rotated stiffness + lumped mass.
+
+    ``log(message)`` receives a line after each generation step, when given."""
+    say = log if log is not None else (lambda m: None)
     pos, tets = box_mesh(n, n, n, 1.0 / n)
     nv = pos.shape[0]
     edges = mesh_edges(tets, nv)
+    say(f"mesh: {nv} vertices, {tets.shape[0]} tets, {edges.shape[0]} edges")
     mu, lam = lame(young, poisson)
     rot = random_rotations(rng_for(seed, S_ROT), tets.shape[0])
-    elem_h = elastic_blocks(pos, tets, rot, mu, lam, rho, h)
+    elem_h = elastic_blocks(pos, tets, rot, mu, lam, rho, h,
+                            progress=lambda d, t: say(f"element blocks {d}/{t}"))
+    say("element blocks done")
     vol, _ = shape_gradients(pos, tets)
     field = fourier_field(rng_for(seed, S_FIELD))
     tags = edge_tags(field, pos, edges, frac)
@@ -421,14 +431,16 @@ CONFIGS = {
 }
 
 
-def make_config(name: str) -> dict:
+def make_config(name: str, log=None) -> dict:
     c = CONFIGS[name]
     if c.get("contact"):
         p = contact_problem(c["seed"])
     else:
-        p = grid_problem(c["n"], c["seed"], c["frac"])
+        p = grid_problem(c["n"], c["seed"], c["frac"], log=log)
     if c.get("drift"):
         with_drift(p)
+        if log is not None:
+            log(f"drift step {p['drift_delta']:.4g} along {np.round(p['drift_dir'], 3).tolist()}")
     p["name"] = name
     return p
 

@@ -267,3 +267,39 @@ def test_post_coarsening_matches_oracle(ctx, name, precision):
     # the derivative is that of the coarsened solve only
     with pytest.raises(agc.AgcError):
         agc.agc_solve_backward(ctx, d.problem(), agc.make_opts(post_iters=2), None, 0, None, None, None, None)
+
+
+@pytest.mark.parametrize("coarsen", [1, 0])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_separate_partial_reduction(ctx, coarsen, precision):
+    """The PCG's separate partial-sum reduction (taken by large systems; forced
+    here through AGC_PCG_REDUCE=1 on a second context) meets the same bars as
+    the in-kernel one and follows the same iterates up to summation order."""
+    import os
+    agc = binding()
+    d = dev(ctx, "c4")
+    os.environ["AGC_PCG_REDUCE"] = "1"
+    try:
+        c_red = agc.Context(0)
+    finally:
+        del os.environ["AGC_PCG_REDUCE"]
+    kw = dict(coarsen=coarsen)
+    if precision == "fp64":
+        kw["rtol"] = 1e-10
+    else:
+        kw.update(precision=agc.AGC_PREC_MIXED, rtol=1e-7)
+    log(f"[reduce] c4 coarsen={coarsen} {precision}")
+    try:
+        x_r, m_r, i_r = run_solve(c_red, d, **kw)
+    finally:
+        c_red.close()
+    x_k, m_k, i_k = run_solve(ctx, d, **kw)
+    assert np.array_equal(m_r, m_k)
+    assert abs(i_r.pcg_iters - i_k.pcg_iters) <= 2
+    m, nc, a_c, b_c, x_ref_c = oracle_solution("c4", coarsen=bool(coarsen))
+    x_ref = x_ref_c[m] if coarsen else x_ref_c
+    err = np.linalg.norm(x_r - x_ref) / np.linalg.norm(x_ref)
+    log(f"   iters {i_r.pcg_iters} (in-kernel {i_k.pcg_iters}) err={err:.2e}")
+    assert err <= (1e-7 if precision == "fp64" else 1e-5)
+    if precision == "fp64" and coarsen:
+        assert osol.relative_residual(a_c, b_c, x_r[oagg.representatives(m, nc)]) <= 1e-8
