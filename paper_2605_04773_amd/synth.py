@@ -35,7 +35,8 @@ POISSON = 0.4
 DENSITY = 1000.0
 H_STEP = 1.0e-2
 
-S_ROT, S_FIELD, S_GRAD, S_W, S_FD, S_JITTER, S_CONTACT, S_DRIFT, S_STATES = range(9)
+S_ROT, S_FIELD, S_GRAD, S_W, S_FD, S_JITTER, S_CONTACT, S_DRIFT, S_STATES, S_NEWTON = range(10)
+GRAVITY = 9.8
 
 
 def rng_for(seed: int, stream: int) -> np.random.Generator:
@@ -419,6 +420,41 @@ def deformation_states(p: dict, wave_amp: float = 2e-4, wave_cycles: float = 3.0
     pol /= np.linalg.norm(pol)
     u_cur = u_cur + wave_amp * (env * np.sin(2.0 * math.pi * (rest @ kw)))[:, None] * pol[None, :]
     return rigid(rest + u_prev), rigid(rest + u_cur)
+
+
+def material(young: float = YOUNG, poisson: float = POISSON, rho: float = DENSITY, h: float = H_STEP) -> dict:
+    mu, lam = lame(young, poisson)
+    return {"mu": mu, "lam": lam, "rho": rho, "h": h}
+
+
+def newton_state(p: dict, spin: float = 1.0, wave_speed: float = 0.2, wave_cycles: float = 3.0,
+                 width: float = 0.15, gravity: bool = True):
+    """Start of one implicit time step on the mesh of p: positions x^t (the rest
+    shape), velocities v^t (a rigid spin of ``spin`` rad/s about a random axis
+    through the centre plus a transverse elastic wave packet of peak speed
+    ``wave_speed`` m/s, ``wave_cycles`` cycles per unit length, Gaussian
+    envelope of width ``width`` around a random point) and external forces
+    f_ext (gravity on the lumped masses, or None).  The strain increment is
+    then large inside the packet and near zero elsewhere."""
+    rng = rng_for(p["seed"], S_NEWTON)
+    rest = p["pos"]
+    c = rest.mean(axis=0)
+    lo, hi = rest.min(axis=0), rest.max(axis=0)
+    axis = rng.standard_normal(3)
+    axis /= np.linalg.norm(axis)
+    v = spin * np.cross(axis[None, :], rest - c)
+    centre = lo + rng.uniform(0.25, 0.75, size=3) * (hi - lo)
+    kw = rng.standard_normal(3)
+    kw *= wave_cycles / np.linalg.norm(kw)
+    pol = np.cross(kw, rng.standard_normal(3))
+    pol /= np.linalg.norm(pol)
+    env = np.exp(-np.sum((rest - centre) ** 2, axis=1) / (width * width))
+    v = v + wave_speed * (env * np.sin(2.0 * math.pi * (rest @ kw)))[:, None] * pol[None, :]
+    f = None
+    if gravity:
+        f = np.zeros_like(rest)
+        f[:, 1] = -GRAVITY * p["mass"]
+    return rest.copy(), v, f
 
 
 # The measured workloads.
