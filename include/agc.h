@@ -319,6 +319,64 @@ agc_status agc_solve_backward(agc_context* ctx, const agc_problem* prob,
                               const double* x, const double* w, double* dg, double* dH,
                               agc_solve_info* info);
 
+/* ------------------------------------------------ the outer Newton loop */
+
+/* One implicit time step's Newton loop (Sec. 3, Eq. 1-2; Alg. overview),
+ * without contact, barrier or friction terms, on the tetrahedra of a mesh.
+ * The incremental potential, divided by h^2, is
+ *   E(x) = sum_v m_v / (2 h^2) |x_v - xhat_v|^2 + sum_e V_e psi(F_e),
+ *   xhat = x^t + h v^t + h^2 M^{-1} f_ext,  m_v = sum of rho V_e / 4,
+ * with co-rotated elasticity psi(F) = mu |F - R|^2 + lambda/2 (tr(R^T F) - 3)^2
+ * (R the rotation of the rotation-variant polar decomposition of F).  The
+ * Hessian proxy is the Hessian with every R held fixed plus the lumped mass
+ * / h^2 (SPD).  Each iteration: gradient and proxy; edge tags from the Green
+ * strain increment against the previous iterate (the first iteration takes
+ * x^t - h v^t); the solve x = agc_solve(...) with d = -x; alpha = 1 halved
+ * until E(x + alpha d) < E(x) (at most 30 halvings, after which the loop
+ * stops without moving); stop when |d|_inf / h <= eps_d. */
+typedef struct agc_newton agc_newton;
+typedef struct { double mu, lambda, rho, h; } agc_material;   /* Lame parameters, density, time step */
+
+/* rest: [n_verts][3] float64 rest positions, copied; edges: [n_edges][2]
+ * int32 (8-byte aligned), copied.  The mesh must outlive the handle; its
+ * elements are the tetrahedra.  A degenerate tetrahedron or an id out of
+ * range gives AGC_ERR_INVALID_ARG.  Synchronises. */
+agc_status agc_newton_create(agc_context* ctx, const agc_mesh* mesh, int64_t n_edges, const int32_t* edges,
+                             const double* rest, const agc_material* mat, agc_newton** out);
+agc_status agc_newton_destroy(agc_context* ctx, agc_newton* nw);
+
+typedef struct {
+  int32_t max_newton;    /* iteration cap                                      */
+  double eps_d;          /* stop when |d|_inf / h <= eps_d                     */
+  double tag_threshold;  /* Green strain increment threshold (paper: 5e-5)      */
+  int32_t coarsen;       /* 1: tags from the strain increment; 0: fine solves    */
+  agc_solve_opts solve;  /* options of every linear solve (timing is ignored)  */
+} agc_newton_opts;
+
+typedef struct {
+  int32_t newton_iters;
+  int32_t halvings;        /* line-search halvings over all iterations          */
+  int32_t pcg_iters;       /* PCG iterations over all linear solves             */
+  int64_t coarse_nodes_sum;/* sum over iterations of the coarse system size      */
+  double energy0, energy;  /* E at x^t and at the result                        */
+  double d_inf;            /* |d|_inf of the last direction                     */
+  float ms_physics, ms_tags, ms_solve, ms_line;   /* host-timed phases          */
+} agc_newton_info;
+
+/* x_t, v_t: [n_verts][3] float64; f_ext: [n_verts][3] float64 or NULL;
+ * x_out: [n_verts][3] float64 out (may not alias the inputs).  info may be
+ * NULL.  Synchronises. */
+agc_status agc_newton_step(agc_context* ctx, agc_newton* nw, const agc_newton_opts* opts, const double* x_t,
+                           const double* v_t, const double* f_ext, double* x_out, agc_newton_info* info);
+
+/* The pieces, for checking: the lumped masses m_v ([n_verts] out); at x with
+ * the predicted positions x_hat, the gradient g ([n_verts][3] out, may be
+ * NULL), the proxy blocks ([n_elems][144] float64 out, 16-byte aligned, may
+ * be NULL) and E ([host] out, may be NULL).  Synchronise. */
+agc_status agc_newton_mass(agc_context* ctx, const agc_newton* nw, double* mass);
+agc_status agc_newton_physics(agc_context* ctx, const agc_newton* nw, const double* x, const double* x_hat,
+                              double* g, double* elem_H, double* energy);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Runs agc_spmv `reps` times between two HIP events on the context's stream

@@ -32,7 +32,8 @@ EXPORTS = (
     "agc_assemble_coarse", "agc_assemble_fine", "agc_matrix_destroy", "agc_matrix_info",
     "agc_matrix_copy", "agc_spmv", "agc_pcg", "agc_prolongate", "agc_restrict", "agc_solve",
     "agc_solve_backward", "agc_time_spmv", "agc_tagger_create", "agc_tagger_destroy", "agc_tag_edges",
-    "agc_assemble_coarse_affine",
+    "agc_assemble_coarse_affine", "agc_newton_create", "agc_newton_destroy", "agc_newton_step",
+    "agc_newton_mass", "agc_newton_physics",
 )
 
 
@@ -80,6 +81,24 @@ class agc_pcg_info(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("rel_res", c_double)]
 
 
+class agc_material(ctypes.Structure):
+    _fields_ = [("mu", c_double), ("lambda_", c_double), ("rho", c_double), ("h", c_double)]
+
+
+class agc_newton_opts(ctypes.Structure):
+    _fields_ = [("max_newton", c_int32), ("eps_d", c_double), ("tag_threshold", c_double), ("coarsen", c_int32),
+                ("solve", agc_solve_opts)]
+
+
+class agc_newton_info(ctypes.Structure):
+    _fields_ = [("newton_iters", c_int32), ("halvings", c_int32), ("pcg_iters", c_int32),
+                ("coarse_nodes_sum", c_int64), ("energy0", c_double), ("energy", c_double), ("d_inf", c_double),
+                ("ms_physics", c_float), ("ms_tags", c_float), ("ms_solve", c_float), ("ms_line", c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2605_04773_amd.build`")
@@ -114,6 +133,11 @@ def _load():
         "agc_solve_backward": (S, [P, POINTER(agc_problem), POINTER(agc_solve_opts), P, c_int32, P, P, P, P,
                                    POINTER(agc_solve_info)]),
         "agc_time_spmv": (S, [P, P, P, P, c_int32, POINTER(c_float)]),
+        "agc_newton_create": (S, [P, P, c_int64, P, P, POINTER(agc_material), POINTER(c_void_p)]),
+        "agc_newton_destroy": (S, [P, P]),
+        "agc_newton_step": (S, [P, P, POINTER(agc_newton_opts), P, P, P, P, POINTER(agc_newton_info)]),
+        "agc_newton_mass": (S, [P, P, P]),
+        "agc_newton_physics": (S, [P, P, P, P, P, P, POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -416,6 +440,72 @@ def agc_solve(ctx: Context, prob: agc_problem, opts: agc_solve_opts, x: torch.Te
     info = agc_solve_info()
     _check(ctx.h, _lib.agc_solve(ctx.h, byref(prob), byref(opts), _ptr(x), _ptr(map_out), byref(info)))
     return info
+
+
+class Newton:
+    """One implicit time step's Newton loop on the tetrahedra of a mesh (agc_newton_*)."""
+
+    def __init__(self, ctx: Context, h, n_verts, n_elems):
+        self.ctx, self.h, self.n_verts, self.n_elems = ctx, h, n_verts, n_elems
+
+    def close(self):
+        if getattr(self, "h", None) and self.ctx.h:
+            _lib.agc_newton_destroy(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def agc_newton_create(ctx: Context, mesh: Mesh, edges: torch.Tensor, rest: torch.Tensor, mu: float, lam: float,
+                      rho: float, h: float) -> Newton:
+    m = edges.shape[0]
+    _dev(edges, torch.int32, (m, 2), "edges", ctx.device)
+    _dev(rest, torch.float64, (mesh.n_verts, 3), "rest", ctx.device)
+    mat = agc_material(float(mu), float(lam), float(rho), float(h))
+    out = c_void_p()
+    _check(ctx.h, _lib.agc_newton_create(ctx.h, mesh.h, int(m), _ptr(edges), _ptr(rest), byref(mat), byref(out)))
+    return Newton(ctx, out, mesh.n_verts, mesh.n_elems)
+
+
+def make_newton_opts(max_newton=50, eps_d=1e-3, tag_threshold=5e-5, coarsen=1, solve=None) -> agc_newton_opts:
+    return agc_newton_opts(int(max_newton), float(eps_d), float(tag_threshold), int(coarsen),
+                           solve if solve is not None else make_opts())
+
+
+def agc_newton_step(ctx: Context, nw: Newton, opts: agc_newton_opts, x_t, v_t, f_ext=None, x_out=None):
+    n = nw.n_verts
+    _dev(x_t, torch.float64, (n, 3), "x_t", ctx.device)
+    _dev(v_t, torch.float64, (n, 3), "v_t", ctx.device)
+    if f_ext is not None:
+        _dev(f_ext, torch.float64, (n, 3), "f_ext", ctx.device)
+    x = torch.empty((n, 3), dtype=torch.float64, device=ctx.device) if x_out is None else x_out
+    _dev(x, torch.float64, (n, 3), "x_out", ctx.device)
+    info = agc_newton_info()
+    _check(ctx.h, _lib.agc_newton_step(ctx.h, nw.h, byref(opts), _ptr(x_t), _ptr(v_t), _ptr(f_ext), _ptr(x),
+                                       byref(info)))
+    return x, info
+
+
+def agc_newton_mass(ctx: Context, nw: Newton) -> torch.Tensor:
+    m = torch.empty(nw.n_verts, dtype=torch.float64, device=ctx.device)
+    _check(ctx.h, _lib.agc_newton_mass(ctx.h, nw.h, _ptr(m)))
+    return m
+
+
+def agc_newton_physics(ctx: Context, nw: Newton, x, x_hat, want_blocks=True):
+    """(g [n,3], elem_H [n_e,144] or None, E) at x with predicted positions x_hat."""
+    n = nw.n_verts
+    _dev(x, torch.float64, (n, 3), "x", ctx.device)
+    _dev(x_hat, torch.float64, (n, 3), "x_hat", ctx.device)
+    g = torch.empty((n, 3), dtype=torch.float64, device=ctx.device)
+    hb = torch.empty((nw.n_elems, 144), dtype=torch.float64, device=ctx.device) if want_blocks else None
+    e = c_double()
+    _check(ctx.h, _lib.agc_newton_physics(ctx.h, nw.h, _ptr(x), _ptr(x_hat), _ptr(g), _ptr(hb), byref(e)))
+    return g, hb, e.value
 
 
 def agc_solve_backward(ctx: Context, prob: agc_problem, opts: agc_solve_opts, map_, n_coarse: int, x, w, dg, dH):

@@ -8,9 +8,6 @@
 
 #include "internal.h"
 
-struct agc_mesh {
-  agc::Mesh m;
-};
 struct agc_matrix {
   agc::Matrix m;
 };

@@ -192,6 +192,10 @@ struct agc_context {
   agc::Matrix solve_fine;      // the fine system for post-coarsening
 };
 
+struct agc_mesh {
+  agc::Mesh m;
+};
+
 // Entry-point frame: a C++ exception never crosses the ABI; its message is
 // kept in the context and its code returned.
 #define API_BEGIN(ctx)                                \

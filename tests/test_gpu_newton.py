@@ -1,0 +1,163 @@
+"""GPU parity of the outer Newton loop (agc_newton_*) against the oracle (Sec. 3, Eq. 1-2; Alg. overview).
+
+Per element and per vertex (masses, gradient, proxy blocks, energy): against
+oracle/newton.py at deformed states that include inverted elements, to
+rounding (relative 1e-10 of each quantity's scale; the rotation comes from
+two different methods, Jacobi on F^T F here and an SVD in the oracle).  The
+loop: with float64 solves to 1e-12 both sides take the same directions, so
+the per-iteration energies and step lengths agree and the results agree to
+1e-9 of the displacement; with coarsening the tags of an element within
+rounding of the threshold could differ, so the coarsened loop is compared
+by its final energy."""
+import numpy as np
+import pytest
+
+from oracle import newton as onw
+from paper_2605_04773_amd import synth
+from tests.gpu_util import binding, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    agc = binding()
+    c = agc.Context(0)
+    yield c
+    c.close()
+
+
+_cases = {}
+
+
+def case(ctx, n):
+    """(p, device tensors, Newton handle) of an n^3 grid."""
+    if n not in _cases:
+        import torch
+        agc = binding()
+        p = synth.grid_problem(n, 40 + n, 0.6)
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(ctx.device, dt)
+        d = {"ev": t(p["elem_verts"], torch.int32), "edges": t(p["edges"], torch.int32),
+             "rest": t(p["pos"], torch.float64), "t": t}
+        d["mesh"] = agc.agc_mesh_create(ctx, p["n_verts"], d["ev"])
+        m = synth.material()
+        d["nw"] = agc.agc_newton_create(ctx, d["mesh"], d["edges"], d["rest"], m["mu"], m["lam"], m["rho"], m["h"])
+        _cases[n] = (p, d)
+    return _cases[n]
+
+
+def _oracle_parts(p):
+    m = synth.material()
+    _, vol, b = onw.rest_shape(p["pos"], p["elem_verts"])
+    mass = onw.lumped_mass(p["n_verts"], p["elem_verts"], vol, m["rho"])
+    return m, vol, b, mass
+
+
+@pytest.mark.parametrize("n", [3, 8])
+def test_mass(ctx, n):
+    agc = binding()
+    p, d = case(ctx, n)
+    _, _, _, mass = _oracle_parts(p)
+    got = agc.agc_newton_mass(ctx, d["nw"]).cpu().numpy()
+    assert np.allclose(got, mass, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("n", [3, 8])
+@pytest.mark.parametrize("state", ["spun", "crushed"])
+def test_physics(ctx, n, state):
+    import torch
+    agc = binding()
+    p, d = case(ctx, n)
+    m, vol, b, mass = _oracle_parts(p)
+    rng = np.random.default_rng(100 + n)
+    rot = synth.random_rotations(rng, 1)[0]
+    x = p["pos"] @ rot.T + 0.3
+    if state == "spun":
+        x = x + 0.02 / n * rng.standard_normal(x.shape)
+    else:   # large deformation: some elements inverted
+        x = x + 0.6 / n * rng.standard_normal(x.shape)
+    x_hat = p["pos"] + 0.01 * rng.standard_normal(x.shape)
+    f = onw.deformation_gradients(x, p["elem_verts"], b)
+    n_inv = int((np.linalg.det(f) < 0).sum())
+    log(f"[newton physics] n={n} {state}: {n_inv} inverted of {f.shape[0]}")
+    if state == "crushed":
+        assert n_inv > 0
+    g, hb, e = agc.agc_newton_physics(ctx, d["nw"], d["t"](x, torch.float64), d["t"](x_hat, torch.float64))
+    g, hb = g.cpu().numpy(), hb.cpu().numpy()
+    args = (x_hat, mass, p["elem_verts"], b, vol, m["mu"], m["lam"], m["h"])
+    g_ref = onw.gradient(x, *args)
+    e_ref = onw.energy(x, *args)
+    h_ref = onw.element_blocks(x, p["elem_verts"], b, vol, m["mu"], m["lam"], m["rho"], m["h"])
+    assert abs(e - e_ref) <= 1e-11 * abs(e_ref)
+    assert np.abs(g - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
+    assert np.abs(hb - h_ref).max() <= 1e-10 * np.abs(h_ref).max()
+    hb3 = hb.reshape(-1, 12, 12)
+    assert np.array_equal(hb3, np.swapaxes(hb3, 1, 2))
+
+
+def _run(ctx, n, coarsen, precision="fp64", **kw):
+    import torch
+    agc = binding()
+    p, d = case(ctx, n)
+    x_t, v_t, f = synth.newton_state(p, wave_speed=0.5)
+    solve = agc.make_opts(rtol=1e-12, coarsen=1) if precision == "fp64" else \
+        agc.make_opts(precision=agc.AGC_PREC_MIXED, rtol=1e-7)
+    opts = agc.make_newton_opts(eps_d=kw.get("eps_d", 1e-4), coarsen=coarsen, solve=solve)
+    t = lambda a: d["t"](a, torch.float64)
+    x, info = agc.agc_newton_step(ctx, d["nw"], opts, t(x_t), t(v_t), t(f))
+    return p, x.cpu().numpy(), info, (x_t, v_t, f)
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_fine_loop_matches_oracle(ctx, n):
+    p, x, info, (x_t, v_t, f) = _run(ctx, n, coarsen=0)
+    mesh = {"n_verts": p["n_verts"], "rest": p["pos"], "tets": p["elem_verts"], "edges": p["edges"]}
+    x_ref, log_ref = onw.time_step(mesh, synth.material(), x_t, v_t, f, eps_d=1e-4, coarsen=False)
+    log(f"[newton fine] n={n}: gpu {info.newton_iters} iters E {info.energy0:.6g} -> {info.energy:.10g}; "
+        f"oracle {len(log_ref)} iters E -> {log_ref[-1]['energy_after']:.10g}")
+    assert info.newton_iters == len(log_ref)
+    assert info.halvings == sum(it["halvings"] for it in log_ref)
+    assert abs(info.energy0 - log_ref[0]["energy"]) <= 1e-11 * abs(log_ref[0]["energy"])
+    assert abs(info.energy - log_ref[-1]["energy_after"]) <= 1e-9 * abs(log_ref[0]["energy"])
+    disp = np.abs(x_ref - x_t).max()
+    assert np.abs(x - x_ref).max() <= 1e-9 * disp
+
+
+@pytest.mark.parametrize("n", [4, 8])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_coarsened_loop(ctx, n, precision):
+    p, x, info, (x_t, v_t, f) = _run(ctx, n, coarsen=1, precision=precision)
+    mesh = {"n_verts": p["n_verts"], "rest": p["pos"], "tets": p["elem_verts"], "edges": p["edges"]}
+    mat = synth.material()
+    x_ref, log_ref = onw.time_step(mesh, mat, x_t, v_t, f, eps_d=1e-4, coarsen=True)
+    xf_ref, logf = onw.time_step(mesh, mat, x_t, v_t, f, eps_d=1e-4, coarsen=False)
+    e0, ef = logf[0]["energy"], logf[-1]["energy_after"]
+    log(f"[newton coarsened] n={n} {precision}: gpu {info.newton_iters} iters, mean coarse size "
+        f"{info.coarse_nodes_sum / info.newton_iters:.0f} of {p['n_verts']}, E -> {info.energy:.10g}; oracle "
+        f"{len(log_ref)} iters E -> {log_ref[-1]['energy_after']:.10g}; fine minimum {ef:.10g}")
+    assert info.energy < info.energy0
+    assert abs(info.energy - log_ref[-1]["energy_after"]) <= 1e-6 * (e0 - ef)
+    assert info.energy - ef <= 1e-3 * (e0 - ef)
+    assert info.coarse_nodes_sum < info.newton_iters * p["n_verts"]
+    if precision == "fp64":
+        assert abs(info.newton_iters - len(log_ref)) <= 1
+
+
+def test_bad_input(ctx):
+    import torch
+    agc = binding()
+    p, d = case(ctx, 3)
+    m = synth.material()
+    with pytest.raises(agc.AgcError):
+        agc.agc_newton_create(ctx, d["mesh"], d["edges"], d["rest"], m["mu"], m["lam"], -1.0, m["h"])
+    flat = d["rest"].clone()
+    flat[:, 2] = 0.0            # every element degenerate
+    with pytest.raises(agc.AgcError):
+        agc.agc_newton_create(ctx, d["mesh"], d["edges"], flat, m["mu"], m["lam"], m["rho"], m["h"])
+    x_t, v_t, f = synth.newton_state(p)
+    t = lambda a: d["t"](a, torch.float64)
+    with pytest.raises(agc.AgcError):
+        agc.agc_newton_step(ctx, d["nw"], agc.make_newton_opts(max_newton=0), t(x_t), t(v_t), t(f))
+    # the handle still works
+    x, info = agc.agc_newton_step(ctx, d["nw"], agc.make_newton_opts(eps_d=1e-3), t(x_t), t(v_t), None)
+    assert info.newton_iters >= 1 and info.energy < info.energy0
