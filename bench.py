@@ -105,6 +105,45 @@ def cpu_baseline(p, rtol):
                       f"numpy/scipy single-threaded"}
 
 
+def newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth):
+    """One implicit time step's Newton loop (no contact): the coarsened loop
+    (tags from the Green strain increment, mixed-precision solves, with 10,
+    3 and no post-coarsening iterations) beside the same loop with fine
+    solves, with the paper's tolerances (PCG 1e-3, |d|_inf / h <= 1e-3 l, l
+    the bounding box diagonal); the state is a body at rest under gravity
+    with a travelling wave packet (localised activity)."""
+    mat = synth.material()
+    nw = agc.agc_newton_create(ctx, mesh, edges, t(p["pos"], torch.float64), mat["mu"], mat["lam"], mat["rho"],
+                               mat["h"])
+    x_t, v_t, f = synth.newton_state(p, spin=0.0)
+    x_t, v_t, f = t(x_t, torch.float64), t(v_t, torch.float64), t(f, torch.float64)
+    diag = float(np.linalg.norm(p["pos"].max(axis=0) - p["pos"].min(axis=0)))
+    res = {}
+    for name, coarsen, post in (("coarsened", 1, 10), ("coarsened_post3", 1, 3), ("coarsened_no_post", 1, 0),
+                                ("fine", 0, 0)):
+        so = agc.make_opts(precision=agc.AGC_PREC_MIXED, rtol=1e-3, inner_rtol=1e-3, post_iters=post)
+        opts = agc.make_newton_opts(eps_d=1e-3 * diag, coarsen=coarsen, solve=so)
+        x_out = torch.empty_like(x_t)
+        ms, info = time_steps(lambda: agc.agc_newton_step(ctx, nw, opts, x_t, v_t, f, x_out)[1],
+                              max(2, args.steps // 3), 1, torch)
+        res[name] = {"ms_per_time_step": round(ms, 3), "newton_iters": info.newton_iters,
+                     "pcg_iters": info.pcg_iters, "halvings": info.halvings,
+                     "mean_coarse_nodes": round(info.coarse_nodes_sum / max(info.newton_iters, 1), 1),
+                     "energy0": info.energy0, "energy": info.energy,
+                     "ms_phases": {"physics": round(info.ms_physics, 3), "tags": round(info.ms_tags, 3),
+                                   "solve": round(info.ms_solve, 3), "line_search": round(info.ms_line, 3)}}
+        log(f"[bench] Newton time step, {name}: {ms:.2f} ms, {info.newton_iters} iterations, "
+            f"{info.pcg_iters} PCG iterations, mean coarse size {res[name]['mean_coarse_nodes']:.0f}, "
+            f"E {info.energy0:.6g} -> {info.energy:.8g}")
+    nw.close()
+    drop = res["fine"]["energy0"] - res["fine"]["energy"]
+    for k in ("coarsened", "coarsened_post3", "coarsened_no_post"):
+        res[k]["speedup_vs_fine"] = round(res["fine"]["ms_per_time_step"] / res[k]["ms_per_time_step"], 3)
+        res[k]["energy_gap_vs_fine"] = (res[k]["energy"] - res["fine"]["energy"]) / drop if drop > 0 else None
+    res["eps_d"] = 1e-3 * diag
+    return res
+
+
 N_DRIFT_SYSTEMS = 10
 
 
@@ -322,6 +361,8 @@ def main():
     log(f"[bench] edge tags (Green strain increment, 5e-5): {ms_tag:.3f} ms, {n_prot / tag_out.numel():.3f} protected")
     extra["tag_ms_per_call"] = round(ms_tag, 4)
     extra["tag_protected_fraction"] = round(n_prot / tag_out.numel(), 4)
+    if "n_tets" not in p:   # the outer Newton loop needs a pure tetrahedral mesh
+        extra["newton"] = newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth)
     if not args.no_compare:
         log("[bench] fine FP64 solve (comparator)")
         fine = solver(rtol=args.rtol_fine, coarsen=0)
