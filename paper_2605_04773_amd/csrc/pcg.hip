@@ -39,7 +39,11 @@
 
 namespace agc {
 
-constexpr int kItems = 4;
+#ifndef AGC_SPMV_ITEMS
+#define AGC_SPMV_ITEMS 4
+#endif
+constexpr int kItems = AGC_SPMV_ITEMS;   // consecutive blocks per thread (a multiple of 4)
+static_assert(kItems % 4 == 0, "blocks per thread: a multiple of 4");
 constexpr int kTile = kWG * kItems;   // blocks per SpMV workgroup
 
 // ------------------------------------------------------------ loads
@@ -72,6 +76,13 @@ __device__ __forceinline__ void load4(const double* p, double o[4]) {
   const vd2 a = stream_load(reinterpret_cast<const vd2*>(p));
   const vd2 b = stream_load(reinterpret_cast<const vd2*>(p) + 1);
   o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+
+// kItems consecutive values, kItems / 4 vector loads
+template <class T>
+__device__ __forceinline__ void load_items(const T* p, T (&o)[kItems]) {
+#pragma unroll
+  for (int h = 0; h < kItems / 4; ++h) load4(p + 4 * h, o + 4 * h);
 }
 
 // The vector the SpMV multiplies, stored in V (double, or float for the
@@ -115,8 +126,8 @@ __device__ __forceinline__ void load_quad_index(int64_t w, const int32_t* __rest
   const int64_t k0 = t0 + (int64_t)threadIdx.x * kItems;
   const int64_t kl = k0 < nnzb ? k0 : 0;
   int32_t r4[kItems], c4[kItems];
-  load4(ri + kl, r4);
-  load4(col + kl, c4);
+  load_items(ri + kl, r4);
+  load_items(col + kl, c4);
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const bool in = k0 + j < nnzb;
@@ -141,7 +152,7 @@ __device__ __forceinline__ void load_quad_vals(int64_t w, const T* __restrict__ 
   const int64_t k0 = w * kTile + (int64_t)threadIdx.x * kItems;
   const int64_t kl = k0 < nnzb ? k0 : 0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) load4(vals + (int64_t)i * stride + kl, q.a[i]);
+  for (int i = 0; i < 9; ++i) load_items(vals + (int64_t)i * stride + kl, q.a[i]);
   // the loads above are issued before the gathers that follow
   __builtin_amdgcn_sched_barrier(0);
 }
