@@ -144,6 +144,44 @@ def newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth):
     return res
 
 
+def extras(args, p, ctx, mesh, edges, tags, ev, t, solver, extra, torch, agc, synth):
+    """The rows reported beside the metric: post-coarsening, affine embedding,
+    edge tagging and one Newton time step."""
+    # the step after prolongation: post-coarsening, 10 fine PCG iterations (reported beside the metric)
+    post = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, post_iters=10)
+    ms_post, pinfo = time_steps(post, max(3, args.steps // 2), 1, torch)
+    log(f"[bench] with post-coarsening (10 fine PCG iterations): {ms_post:.3f} ms/solve, fine residual "
+        f"{pinfo.fine_rel_res0:.2e} -> {pinfo.fine_rel_res:.2e}")
+    extra["post_coarsening"] = {"iters": pinfo.post_iters, "ms_per_solve": round(ms_post, 4),
+                                "fine_rel_res_before": pinfo.fine_rel_res0, "fine_rel_res_after": pinfo.fine_rel_res}
+    # the paper's main variant: 12-DoF affine nodes for aggregates of more than 32 vertices
+    aff = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, affine_threshold=32)
+    ms_aff, ainfo = time_steps(aff, max(3, args.steps // 2), 1, torch)
+    log(f"[bench] with affine embedding (> 32 members): {ms_aff:.3f} ms/solve, {ainfo.n_affine} affine nodes, "
+        f"{ainfo.n_blocks} block rows, pcg_iters={ainfo.pcg_iters} rel_res={ainfo.rel_res:.2e}")
+    extra["affine_embedding"] = {"threshold": 32, "ms_per_solve": round(ms_aff, 4), "n_affine": ainfo.n_affine,
+                                 "block_rows": ainfo.n_blocks, "pcg_iters": ainfo.pcg_iters,
+                                 "rel_res_fp64": ainfo.rel_res}
+    # the step before the map: Green-strain-increment tags for two synthetic iterates
+    n_tets = int(p.get("n_tets", p["elem_verts"].shape[0]))
+    tagger = agc.agc_tagger_create(ctx, p["n_verts"], ev[:n_tets].contiguous(), t(p["pos"], torch.float64), edges)
+    xp, xc = synth.deformation_states(p)
+    xp, xc = t(xp, torch.float64), t(xc, torch.float64)
+    tag_out = torch.empty_like(tags)
+
+    def tag_step():
+        agc.agc_tag_edges(ctx, tagger, xc, xp, 5e-5, tag_out, count=False)
+        return None
+    ms_tag, _ = time_steps(tag_step, max(args.steps, 10), 2, torch)
+    _, n_prot = agc.agc_tag_edges(ctx, tagger, xc, xp, 5e-5, tag_out)
+    tagger.close()
+    log(f"[bench] edge tags (Green strain increment, 5e-5): {ms_tag:.3f} ms, {n_prot / tag_out.numel():.3f} protected")
+    extra["tag_ms_per_call"] = round(ms_tag, 4)
+    extra["tag_protected_fraction"] = round(n_prot / tag_out.numel(), 4)
+    if "n_tets" not in p:   # the outer Newton loop needs a pure tetrahedral mesh
+        extra["newton"] = newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth)
+
+
 N_DRIFT_SYSTEMS = 10
 
 
@@ -238,6 +276,9 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-4, help="mixed: tolerance of each inner solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the fine and FP64 comparators")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip post-coarsening, affine embedding, tagging and the Newton step (profiling runs: "
+                         "the PCG SpMV then runs on the measured coarse matrix only)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates the HBM counters), then exit")
     args = ap.parse_args()
@@ -330,39 +371,8 @@ def main():
         f"{ti.spmv_launches} = {achieved:.0f} GB/s")
 
     extra = {"solution_error": {"coarse_mixed": err_mixed}}
-    # the step after prolongation: post-coarsening, 10 fine PCG iterations (reported beside the metric)
-    post = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, post_iters=10)
-    ms_post, pinfo = time_steps(post, max(3, args.steps // 2), 1, torch)
-    log(f"[bench] with post-coarsening (10 fine PCG iterations): {ms_post:.3f} ms/solve, fine residual "
-        f"{pinfo.fine_rel_res0:.2e} -> {pinfo.fine_rel_res:.2e}")
-    extra["post_coarsening"] = {"iters": pinfo.post_iters, "ms_per_solve": round(ms_post, 4),
-                                "fine_rel_res_before": pinfo.fine_rel_res0, "fine_rel_res_after": pinfo.fine_rel_res}
-    # the paper's main variant: 12-DoF affine nodes for aggregates of more than 32 vertices
-    aff = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, affine_threshold=32)
-    ms_aff, ainfo = time_steps(aff, max(3, args.steps // 2), 1, torch)
-    log(f"[bench] with affine embedding (> 32 members): {ms_aff:.3f} ms/solve, {ainfo.n_affine} affine nodes, "
-        f"{ainfo.n_blocks} block rows, pcg_iters={ainfo.pcg_iters} rel_res={ainfo.rel_res:.2e}")
-    extra["affine_embedding"] = {"threshold": 32, "ms_per_solve": round(ms_aff, 4), "n_affine": ainfo.n_affine,
-                                 "block_rows": ainfo.n_blocks, "pcg_iters": ainfo.pcg_iters,
-                                 "rel_res_fp64": ainfo.rel_res}
-    # the step before the map: Green-strain-increment tags for two synthetic iterates
-    n_tets = int(p.get("n_tets", p["elem_verts"].shape[0]))
-    tagger = agc.agc_tagger_create(ctx, p["n_verts"], ev[:n_tets].contiguous(), t(p["pos"], torch.float64), edges)
-    xp, xc = synth.deformation_states(p)
-    xp, xc = t(xp, torch.float64), t(xc, torch.float64)
-    tag_out = torch.empty_like(tags)
-
-    def tag_step():
-        agc.agc_tag_edges(ctx, tagger, xc, xp, 5e-5, tag_out, count=False)
-        return None
-    ms_tag, _ = time_steps(tag_step, max(args.steps, 10), 2, torch)
-    _, n_prot = agc.agc_tag_edges(ctx, tagger, xc, xp, 5e-5, tag_out)
-    tagger.close()
-    log(f"[bench] edge tags (Green strain increment, 5e-5): {ms_tag:.3f} ms, {n_prot / tag_out.numel():.3f} protected")
-    extra["tag_ms_per_call"] = round(ms_tag, 4)
-    extra["tag_protected_fraction"] = round(n_prot / tag_out.numel(), 4)
-    if "n_tets" not in p:   # the outer Newton loop needs a pure tetrahedral mesh
-        extra["newton"] = newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth)
+    if not args.no_extras:
+        extras(args, p, ctx, mesh, edges, tags, ev, t, solver, extra, torch, agc, synth)
     if not args.no_compare:
         log("[bench] fine FP64 solve (comparator)")
         fine = solver(rtol=args.rtol_fine, coarsen=0)
