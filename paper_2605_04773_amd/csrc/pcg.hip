@@ -17,10 +17,12 @@
 // carries s = A p, so that both inner products of an iteration, gamma =
 // r^T z and delta = z^T A z, are known before any vector changes, and the
 // only vector the SpMV gathers is z.  In exact arithmetic the iterates are
-// those of standard PCG.  z = D^{-1} r is stored in the matrix's value type:
-// with a float32 matrix the SpMV then gathers 12 bytes per column instead
-// of 24, and the iteration is PCG with the preconditioner's output rounded
-// to float32 (r, x, p, s and every inner product stay float64).  Two
+// those of standard PCG.  z = D^{-1} r, r, p and s are stored in the
+// matrix's value type: with a float32 matrix (the inner solve of the mixed
+// path, which only has to reach a loose tolerance before float64
+// refinement) the SpMV gathers 12 bytes per column instead of 24 and the
+// update moves 72 bytes per row less; each stored vector is rounded once and
+// used as stored, while x, A z and every inner product stay float64.  Two
 // launches per iteration j (plus one tiny check per chunk):
 //   K_1  w = A z_j and a partial z_j^T w per workgroup.
 //   K_2  reduce the partials -> gamma_j, r_j^T r_j, delta_j; stop test;
@@ -575,8 +577,8 @@ __device__ __forceinline__ void apply3(const double m[6], const double v[3], dou
 template <class Z>
 __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, const double* __restrict__ q,
                                                   const double* __restrict__ dinv, int32_t n, double* __restrict__ x,
-                                                  double* __restrict__ r, Z* __restrict__ z,
-                                                  double* __restrict__ p, double* __restrict__ sv,
+                                                  Z* __restrict__ r, Z* __restrict__ z,
+                                                  Z* __restrict__ p, Z* __restrict__ sv,
                                                   double* __restrict__ pb) {
   __shared__ double lds[3 * kWaves];
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
@@ -587,17 +589,17 @@ __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, 
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double bk = b[3 * i + k];
-      rv[k] = q ? bk - q[3 * i + k] : bk;
+      rv[k] = (double)(Z)(q ? bk - q[3 * i + k] : bk);   // the stored r, as every later use sees it
       t[2] += bk * bk;
     }
     apply3(m, rv, zv);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       zv[k] = (double)(Z)zv[k];   // the stored z is the one every inner product sees
-      r[3 * i + k] = rv[k];
+      r[3 * i + k] = (Z)rv[k];
       z[3 * i + k] = (Z)zv[k];
-      p[3 * i + k] = 0.0;
-      sv[3 * i + k] = 0.0;
+      p[3 * i + k] = (Z)0;
+      sv[3 * i + k] = (Z)0;
       if (!q) x[3 * i + k] = 0.0;
       t[0] += rv[k] * zv[k];
       t[1] += rv[k] * rv[k];
@@ -672,9 +674,9 @@ __global__ __launch_bounds__(kWG) void k_pcg_reduce(const double* __restrict__ p
 template <class Z>
 __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __restrict__ rp, int32_t n,
                                                     const double* __restrict__ wy, const double* __restrict__ carry,
-                                                    const double* __restrict__ dinv, double* __restrict__ p,
-                                                    double* __restrict__ sv, double* __restrict__ x,
-                                                    double* __restrict__ r, Z* __restrict__ z,
+                                                    const double* __restrict__ dinv, Z* __restrict__ p,
+                                                    Z* __restrict__ sv, double* __restrict__ x,
+                                                    Z* __restrict__ r, Z* __restrict__ z,
                                                     const double* __restrict__ pa, unsigned ga,
                                                     const double* __restrict__ pb_in, unsigned gin,
                                                     double* __restrict__ pb_out,
@@ -735,13 +737,14 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
     double zn[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      pv[k] = zv[k] + beta * pv[k];
-      sw[k] = wv[k] + beta * sw[k];
-      p[3 * i + k] = pv[k];
-      sv[3 * i + k] = sw[k];
+      // p, s and r are stored in Z; each is rounded once and used as stored
+      pv[k] = (double)(Z)(zv[k] + beta * pv[k]);
+      sw[k] = (double)(Z)(wv[k] + beta * sw[k]);
+      p[3 * i + k] = (Z)pv[k];
+      sv[3 * i + k] = (Z)sw[k];
       x[3 * i + k] = xv[k] + alpha * pv[k];
-      rv[k] = rv[k] - alpha * sw[k];
-      r[3 * i + k] = rv[k];
+      rv[k] = (double)(Z)(rv[k] - alpha * sw[k]);
+      r[3 * i + k] = (Z)rv[k];
     }
     apply3(m, rv, zn);
 #pragma unroll
@@ -782,11 +785,15 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   *rel = 0.0;
   if (n == 0) return AGC_OK;
   double* dinv = c->ws.get<double>("pcg.dinv", 6 * (int64_t)n);
-  double* r = c->ws.get<double>("pcg.r", n3);
-  // z in the matrix's value type (see the top of this file)
-  void* z = a.dtype == AGC_F64 ? (void*)c->ws.get<double>("pcg.z", n3) : (void*)c->ws.get<float>("pcg.z32", n3);
-  double* p = c->ws.get<double>("pcg.p", n3);
-  double* sv = c->ws.get<double>("pcg.s", n3);
+  // z, r, p and s in the matrix's value type (see the top of this file)
+  const bool f64 = a.dtype == AGC_F64;
+  auto zvec = [&](const char* name) {
+    return f64 ? (void*)c->ws.get<double>(name, n3) : (void*)c->ws.get<float>(std::string(name) + "32", n3);
+  };
+  void* z = zvec("pcg.z");
+  void* r = zvec("pcg.r");
+  void* p = zvec("pcg.p");
+  void* sv = zvec("pcg.s");
   double* w = c->ws.get<double>("pcg.w", n3);
   const unsigned gr = blocks_for(n, kWG);
   const unsigned gs = blocks_for(a.nnzb, kTile);
@@ -813,9 +820,11 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   AGC_LAUNCH_CHECK();
   if (!x_zero) spmv(c, a, x, w);   // w = A x0
   if (a.dtype == AGC_F64)
-    k_pcg_init<double><<<gr, kWG, 0, c->stream>>>(b, x_zero ? nullptr : w, dinv, n, x, r, (double*)z, p, sv, pbs[0]);
+    k_pcg_init<double><<<gr, kWG, 0, c->stream>>>(b, x_zero ? nullptr : w, dinv, n, x, (double*)r, (double*)z,
+                                                  (double*)p, (double*)sv, pbs[0]);
   else
-    k_pcg_init<float><<<gr, kWG, 0, c->stream>>>(b, x_zero ? nullptr : w, dinv, n, x, r, (float*)z, p, sv, pbs[0]);
+    k_pcg_init<float><<<gr, kWG, 0, c->stream>>>(b, x_zero ? nullptr : w, dinv, n, x, (float*)r, (float*)z,
+                                                 (float*)p, (float*)sv, pbs[0]);
   AGC_LAUNCH_CHECK();
   k_pcg_check<<<1, kWG, 0, c->stream>>>(0, pbs[0], gr, st, rtol);
   AGC_LAUNCH_CHECK();
@@ -850,10 +859,12 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
         gin = ga = kReduceSlices;
       }
       if (a.dtype == AGC_F64)
-        k_pcg_update<double><<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, p, sv, x, r, (double*)z, pa_in,
+        k_pcg_update<double><<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, (double*)p, (double*)sv, x,
+                                                        (double*)r, (double*)z, pa_in,
                                                         ga, pb_in, gin, pbs[(j + 1) & 1], st, rtol);
       else
-        k_pcg_update<float><<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, p, sv, x, r, (float*)z, pa_in,
+        k_pcg_update<float><<<gr, kWG, 0, c->stream>>>(j, a.rp(), n, w, carry, dinv, (float*)p, (float*)sv, x,
+                                                       (float*)r, (float*)z, pa_in,
                                                        ga, pb_in, gin, pbs[(j + 1) & 1], st, rtol);
     }
     launched += chunk;
