@@ -78,12 +78,14 @@ struct Mesh {
 constexpr int kMaxChunk = 256;   // PCG iterations enqueued between two host checks
 
 // Device PCG scalars.
+constexpr int kRrRing = 16;
 struct PcgState {
   double rz_hist[2];              // gamma_j = r_j^T z_j, by parity of j
   double alpha_hist[2];           // alpha_j, by parity of j
   double rr, bb, tol2;
   int32_t iter, max_iter, done;   // done: 0 running, 1 converged, 2 max_iter, 3 breakdown
   int32_t pad;
+  double rr_ring[kRrRing];        // r_j^T r_j at slot j % kRrRing (the host's convergence-rate estimate)
 };
 
 // ----------------------------------------------------------- primitives

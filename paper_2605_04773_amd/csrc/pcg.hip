@@ -556,6 +556,7 @@ __device__ __forceinline__ int stop_scalars(int64_t j, const double* t, PcgState
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->iter = (int32_t)j;
     st->rr = t[1];
+    st->rr_ring[j % kRrRing] = t[1];
     if (done) st->done = done;
   }
   return done;
@@ -775,6 +776,8 @@ __global__ __launch_bounds__(kWG) void k_pcg_check(int64_t j, const double* __re
 }
 
 constexpr int kFirstChunk = 16;
+constexpr int kRateSpan = 8;   // iterations over which the host measures the residual's decay
+static_assert(kRateSpan < kRrRing, "the ring holds the span");
 constexpr int kTimedReplays = 20;   // SpMV launches timed per PCG solve when kernel timing is on
 
 int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters,
@@ -831,15 +834,14 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
 
   // The host enqueues iterations in chunks and reads the device scalars (and
   // the block-Jacobi error word) in between.  After the first chunk, the
-  // chunk length is the number of iterations the residual's decay over the
-  // last chunk still needs, with a margin, but at most half the number
-  // already run: CG speeds up as it goes, so an early rate overestimates, and a
-  // launch after convergence, though it only reads a flag, still costs the
-  // host's enqueue time.
+  // chunk length is the number of iterations the residual's current decay
+  // (over the last kRateSpan iterations, from the ring of r^T r values) still
+  // needs, with a margin, but at most the number already run: CG speeds up
+  // as it goes, so an early rate overestimates, and a launch after
+  // convergence, though it only reads a flag, still costs the host's enqueue
+  // time, while a host round trip costs that of ~5-10 iterations.
   int64_t launched = 0;
   int chunk = kFirstChunk;
-  int prev_it = 0;
-  double prev_rr = 0.0;
   for (;;) {
     for (int it = 0; it < chunk; ++it) {
       const int64_t j = launched + it;
@@ -877,17 +879,15 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
     if (hs->done) break;
     // the device stops at max_iter; this only guards the host against a lost state
     if (launched > (int64_t)max_iter + 64) throw Error(AGC_ERR_DEVICE, "PCG state did not advance");
-    if (prev_rr == 0.0 && x_zero) prev_rr = hs->bb;   // r_0 = b
     double want = 2.0 * chunk;
-    if (hs->iter > prev_it && hs->rr > 0.0 && prev_rr > 0.0 && hs->rr < prev_rr) {
-      const double rate = log(hs->rr / prev_rr) / (double)(hs->iter - prev_it);
-      want = 1.25 * log(hs->tol2 / hs->rr) / rate + 2.0;
+    const int span = hs->iter < kRateSpan ? hs->iter : kRateSpan;
+    const double rr_then = span > 0 ? hs->rr_ring[(hs->iter - span) % kRrRing] : 0.0;
+    if (span > 0 && hs->rr > 0.0 && rr_then > hs->rr) {
+      const double rate = log(hs->rr / rr_then) / (double)span;
+      want = 1.1 * log(hs->tol2 / hs->rr) / rate + 2.0;
     }
-    const int64_t half = launched / 2;
-    const int cap = half < kFirstChunk ? kFirstChunk : (half > kMaxChunk ? kMaxChunk : (int)half);
+    const int cap = launched < kFirstChunk ? kFirstChunk : (launched > kMaxChunk ? kMaxChunk : (int)launched);
     chunk = want < 4.0 ? 4 : (want > cap ? cap : (int)ceil(want));
-    prev_it = hs->iter;
-    prev_rr = hs->rr;
   }
   if (c->kernel_timing && launched > 0) {
     // The SpMV kernel of the iterations, replayed back to back on the final
