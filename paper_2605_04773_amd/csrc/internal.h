@@ -198,6 +198,18 @@ struct agc_mesh {
   agc::Mesh m;
 };
 
+// Static data of the strain-increment tags (tagging.hip); the destructor
+// releases the device buffers, also when creation fails half way.
+struct agc_tagger {
+  int32_t n = 0;
+  int64_t ne = 0, m = 0, nu = 0;
+  agc::DevBuf tets, dminv, tedge, ekey, hot, count;
+  void release() {
+    tets.release(); dminv.release(); tedge.release(); ekey.release(); hot.release(); count.release();
+  }
+  ~agc_tagger() { release(); }
+};
+
 // Entry-point frame: a C++ exception never crosses the ABI; its message is
 // kept in the context and its code returned.
 #define API_BEGIN(ctx)                                \

@@ -225,11 +225,11 @@ __global__ __launch_bounds__(kWG) void k_nw_vertex(const double* __restrict__ x,
 }
 
 // out[0] = the element partials + the vertex partials, each in order
-__global__ __launch_bounds__(kWG) void k_nw_total(const double* __restrict__ ep, unsigned ge_, const double* __restrict__ vp,
+__global__ __launch_bounds__(kWG) void k_nw_total(const double* __restrict__ ep, unsigned gep, const double* __restrict__ vp,
                                                   unsigned gv, double* __restrict__ out) {
   __shared__ double lds[kWaves];
   double a = 0.0, b = 0.0;
-  for (unsigned i = threadIdx.x; i < ge_; i += kWG) a += ep[i];
+  for (unsigned i = threadIdx.x; i < gep; i += kWG) a += ep[i];
   for (unsigned i = threadIdx.x; i < gv; i += kWG) b += vp[i];
   a = wg_sum(a, lds);
   b = wg_sum(b, lds);
@@ -283,6 +283,11 @@ struct agc_newton {
   agc::DevBuf edges, rest, bvec, vol, mass, vptr, corner;
   void release() {
     edges.release(); rest.release(); bvec.release(); vol.release(); mass.release(); vptr.release(); corner.release();
+  }
+  // releases the buffers and the tagger, also when creation fails half way
+  ~agc_newton() {
+    release();
+    delete tagger;
   }
 };
 
@@ -421,8 +426,6 @@ agc_status agc_newton_create(agc_context* c, const agc_mesh* mesh, int64_t n_edg
 
 agc_status agc_newton_destroy(agc_context* c, agc_newton* nw) {
   if (!c || !nw) return AGC_ERR_INVALID_ARG;
-  if (nw->tagger) agc_tagger_destroy(c, nw->tagger);
-  nw->release();
   delete nw;
   return AGC_OK;
 }

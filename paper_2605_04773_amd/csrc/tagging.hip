@@ -193,14 +193,6 @@ __global__ void k_tag_out(const uint32_t* __restrict__ ekey, const uint8_t* __re
 
 // ------------------------------------------------------------------- ABI
 
-struct agc_tagger {
-  int32_t n = 0;
-  int64_t ne = 0, m = 0, nu = 0;
-  agc::DevBuf tets, dminv, tedge, ekey, hot, count;
-  void release() {
-    tets.release(); dminv.release(); tedge.release(); ekey.release(); hot.release(); count.release();
-  }
-};
 
 extern "C" {
 
@@ -270,8 +262,7 @@ agc_status agc_tagger_create(agc_context* c, int32_t n_verts, int64_t n_tets, co
 
 agc_status agc_tagger_destroy(agc_context* c, agc_tagger* t) {
   if (!c || !t) return AGC_ERR_INVALID_ARG;
-  t->release();
-  delete t;
+  delete t;   // releases its buffers
   return AGC_OK;
 }
 
