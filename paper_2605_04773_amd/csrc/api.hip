@@ -526,7 +526,8 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   double fine_rel0 = 0.0, fine_rel = 0.0;
   if (o->post_iters > 0 && R.map) {
     agc::Matrix& F = c->solve_fine;
-    agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, F);
+    // the coarse assembly just gathered the fine upper blocks of these element blocks
+    agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, F, nullptr, true);
     const int64_t n3 = 3 * (int64_t)n;
     double* y = c->ws.get<double>("post.y", n3);
     double* r = c->ws.get<double>("post.r", n3);

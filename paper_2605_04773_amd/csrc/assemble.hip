@@ -390,7 +390,8 @@ static Acc* fine_upper(agc_context* c, const Mesh& m, const void* eh, int32_t h_
 
 // The fine matrix borrows the mesh's static pattern (no copy per assembly).
 void assemble_fine(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, int32_t out_dtype,
-                   Matrix& out, Matrix* out32) {
+                   Matrix& out, Matrix* out32, bool reuse_upper) {
+  AGC_REQUIRE(!reuse_upper || out_dtype == AGC_F64, "reused fine blocks are float64");
   AGC_REQUIRE(!out32 || out_dtype == AGC_F64, "a float32 companion needs a float64 matrix");
   const int32_t n = m.n_verts;
   const int64_t nnz = m.ff_nnzb;
@@ -398,7 +399,7 @@ void assemble_fine(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtyp
   out.borrow_pattern((const int32_t*)m.ff_row_ptr.p, (const int32_t*)m.ff_col.p, (const int32_t*)m.ff_rowidx.p,
                      (const int32_t*)m.ff_diag.p);
   if (out_dtype == AGC_F64) {
-    double* F = fine_upper<double>(c, m, eh, h_dtype);
+    double* F = reuse_upper ? c->ws.get<double>("asm.F64", 9 * m.nf) : fine_upper<double>(c, m, eh, h_dtype);
     float* v32 = companion32(out, out32);
     k_fill_vals<double><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>((const uint32_t*)m.ff_src.p, nnz, F, m.nf,
                                                                     (double*)out.vals.p, out.stride, v32);

@@ -144,8 +144,10 @@ void affine_prolongate(agc_context* c, int32_t n, const AffineMap& am, const dou
 void mesh_build(agc_context* c, Mesh& m, int32_t n_verts, int64_t n_elems, const int32_t* ev);
 // out32 (float64 output only, may be null) receives the same matrix rounded
 // to float32; it borrows out's pattern, so out must outlive its use.
+// reuse_upper: take the fine upper blocks that the last float64 assembly of
+// the same element blocks left in the workspace instead of gathering them again
 void assemble_fine(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
-                   int32_t out_dtype, Matrix& out, Matrix* out32 = nullptr);
+                   int32_t out_dtype, Matrix& out, Matrix* out32 = nullptr, bool reuse_upper = false);
 void assemble_coarse(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
                      const int32_t* map, int32_t n_c, int32_t out_dtype, Matrix& out,
                      Matrix* out32 = nullptr);
