@@ -125,15 +125,38 @@ struct Material {
   double mu, lam, rho, h;
 };
 
-// Per element: V psi into a per-workgroup partial; with FULL also the element
-// gradient ge[e][12] and, if H is not null, the proxy block H[e][144].
-template <bool FULL>
+// Per element: V psi into a per-workgroup partial; MODE >= 1 also the
+// element gradient ge[e][12]; MODE 2 also the proxy blocks H[e][144].  For
+// the blocks each thread leaves what its element's 144 entries need in LDS
+// (R b_a, b_a, lam V, 2 mu V, the lumped mass / h^2), and the workgroup then
+// writes its kWG consecutive blocks with coalesced 16-byte stores, each
+// entry formed from LDS: a thread's own 144 stores would each touch a
+// different 1152-byte block.
+struct ElemCoef {
+  double rb[12], b[12], lv, mv, mass;
+};
+
+__device__ __forceinline__ double proxy_entry(const ElemCoef& q, int row, int col) {
+  const int a = row / 3, i = row - 3 * a, c = col / 3, j = col - 3 * c;
+  // every product is formed symmetrically in (a, i) <-> (c, j), so the block
+  // is bitwise symmetric
+  double h = q.lv * (q.rb[3 * a + i] * q.rb[3 * c + j]);
+  if (i == j) {
+    const double bb = q.mv * (q.b[3 * a] * q.b[3 * c] + q.b[3 * a + 1] * q.b[3 * c + 1] + q.b[3 * a + 2] * q.b[3 * c + 2]);
+    h += bb + (a == c ? q.mass : 0.0);
+  }
+  return h;
+}
+
+template <int MODE>
 __global__ __launch_bounds__(kWG) void k_nw_elem(const double* __restrict__ x, const int32_t* __restrict__ tets,
                                                  const double* __restrict__ bvec, const double* __restrict__ vol,
                                                  int64_t ne, Material mt, double* __restrict__ ge,
                                                  double* __restrict__ H, double* __restrict__ epart) {
   __shared__ double lds[kWaves];
-  const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  __shared__ ElemCoef coef[MODE == 2 ? kWG : 1];
+  const int64_t e0 = (int64_t)blockIdx.x * kWG;
+  const int64_t e = e0 + threadIdx.x;
   double en = 0.0;
   if (e < ne) {
     double xa[4][3], b[4][3];
@@ -157,37 +180,36 @@ __global__ __launch_bounds__(kWG) void k_nw_elem(const double* __restrict__ x, c
       }
     const double V = vol[e];
     en = V * (mt.mu * d2 + 0.5 * mt.lam * tr * tr);
-    if (FULL) {
+    if (MODE >= 1) {
       double p[3][3];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) p[i][j] = 2.0 * mt.mu * (f[i][j] - r[i][j]) + mt.lam * tr * r[i][j];
       for (int a = 0; a < 4; ++a)
         for (int i = 0; i < 3; ++i)
           ge[12 * e + 3 * a + i] = V * (p[i][0] * b[a][0] + p[i][1] * b[a][1] + p[i][2] * b[a][2]);
-      if (H) {
-        double rb[4][3];
-        for (int a = 0; a < 4; ++a)
-          for (int i = 0; i < 3; ++i) rb[a][i] = r[i][0] * b[a][0] + r[i][1] * b[a][1] + r[i][2] * b[a][2];
-        const double mass = mt.rho * V / (4.0 * mt.h * mt.h);
-        const double lv = mt.lam * V, mv = 2.0 * mt.mu * V;
-        double* he = H + 144 * e;
-        for (int a = 0; a < 4; ++a)
-          for (int i = 0; i < 3; ++i) {
-            double row[12];
-            for (int c = 0; c < 4; ++c) {
-              // every product is formed symmetrically in (a, i) <-> (c, j), so the
-              // block is bitwise symmetric
-              const double bb = mv * (b[a][0] * b[c][0] + b[a][1] * b[c][1] + b[a][2] * b[c][2]);
-              for (int j = 0; j < 3; ++j) {
-                double h = lv * (rb[a][i] * rb[c][j]);
-                if (i == j) h += bb + (a == c ? mass : 0.0);
-                row[3 * c + j] = h;
-              }
-            }
-            double2* dst = reinterpret_cast<double2*>(he + 12 * (3 * a + i));
-            for (int k = 0; k < 6; ++k) dst[k] = make_double2(row[2 * k], row[2 * k + 1]);
-          }
-      }
+    }
+    if (MODE == 2) {
+      ElemCoef& q = coef[threadIdx.x];
+      for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 3; ++i) {
+          q.rb[3 * a + i] = r[i][0] * b[a][0] + r[i][1] * b[a][1] + r[i][2] * b[a][2];
+          q.b[3 * a + i] = b[a][i];
+        }
+      q.lv = mt.lam * V;
+      q.mv = 2.0 * mt.mu * V;
+      q.mass = mt.rho * V / (4.0 * mt.h * mt.h);
+    }
+  }
+  if (MODE == 2) {
+    __syncthreads();
+    const int64_t cnt = ne - e0 < kWG ? ne - e0 : kWG;   // elements of this workgroup
+    double2* dst = reinterpret_cast<double2*>(H + 144 * e0);
+    for (int64_t k2 = threadIdx.x; k2 < 72 * cnt; k2 += kWG) {   // entries 2 k2 and 2 k2 + 1
+      const int el = (int)(k2 / 72);
+      const int k = (int)(2 * k2 - 144 * (int64_t)el);   // even: both entries lie in one row
+      const int row = k / 12, col = k - 12 * row;
+      const ElemCoef& q = coef[el];
+      dst[k2] = make_double2(proxy_entry(q, row, col), proxy_entry(q, row, col + 1));
     }
   }
   const double s = wg_sum(en, lds);
@@ -315,7 +337,7 @@ NwBufs nw_bufs(agc_context* c, const agc_newton* nw, bool with_h) {
 // E(x) [host]; synchronises
 double nw_energy(agc_context* c, const agc_newton* nw, const NwBufs& b, const double* x, const double* xhat) {
   if (nw->ne > 0)
-    k_nw_elem<false><<<b.gel, kWG, 0, c->stream>>>(x, (const int32_t*)nw->mesh->m.elem_verts.p, (const double*)nw->bvec.p,
+    k_nw_elem<0><<<b.gel, kWG, 0, c->stream>>>(x, (const int32_t*)nw->mesh->m.elem_verts.p, (const double*)nw->bvec.p,
                                                   (const double*)nw->vol.p, nw->ne, nw->mt, nullptr, nullptr, b.ep);
   k_nw_vertex<<<b.gvl, kWG, 0, c->stream>>>(x, xhat, (const double*)nw->mass.p, (const uint32_t*)nw->vptr.p,
                                             (const uint32_t*)nw->corner.p, nullptr, nw->n, nw->mt.h, nullptr, b.vp);
@@ -331,8 +353,12 @@ double nw_energy(agc_context* c, const agc_newton* nw, const NwBufs& b, const do
 void nw_physics(agc_context* c, const agc_newton* nw, const NwBufs& b, const double* x, const double* xhat, double* g,
                 double* H) {
   if (nw->ne > 0)
-    k_nw_elem<true><<<b.gel, kWG, 0, c->stream>>>(x, (const int32_t*)nw->mesh->m.elem_verts.p, (const double*)nw->bvec.p,
-                                                 (const double*)nw->vol.p, nw->ne, nw->mt, b.ge, H, b.ep);
+    if (H)
+      k_nw_elem<2><<<b.gel, kWG, 0, c->stream>>>(x, (const int32_t*)nw->mesh->m.elem_verts.p, (const double*)nw->bvec.p,
+                                                (const double*)nw->vol.p, nw->ne, nw->mt, b.ge, H, b.ep);
+    else
+      k_nw_elem<1><<<b.gel, kWG, 0, c->stream>>>(x, (const int32_t*)nw->mesh->m.elem_verts.p, (const double*)nw->bvec.p,
+                                                (const double*)nw->vol.p, nw->ne, nw->mt, b.ge, nullptr, b.ep);
   k_nw_vertex<<<b.gvl, kWG, 0, c->stream>>>(x, xhat, (const double*)nw->mass.p, (const uint32_t*)nw->vptr.p,
                                             (const uint32_t*)nw->corner.p, b.ge, nw->n, nw->mt.h, g, b.vp);
   AGC_LAUNCH_CHECK();
