@@ -66,6 +66,21 @@ typedef struct agc_matrix agc_matrix;   /* assembled BSR 3x3 matrix, device resi
  * size, "0" = inside the update kernel always, "1" = in a separate reduction
  * kernel always.  The two differ only in summation order. */
 agc_status agc_create(agc_context** ctx, int32_t device, void* stream);
+
+/* Device memory for the buffers the context allocates from now on (its
+ * workspace, the matrices it returns, and the meshes, taggers and Newton
+ * handles created through it) comes from alloc(bytes, user) and goes back
+ * through free(ptr, user), e.g. a framework's caching allocator, instead of
+ * hipMalloc / hipFree; both NULL restores hipMalloc.  Buffers keep the
+ * source they were allocated from.  Blocks are requested and returned in the
+ * order of the context's stream: a stream-ordered allocator must serve that
+ * stream.  alloc returning NULL gives AGC_ERR_OUT_OF_MEMORY.  The functions
+ * must stay callable until every block they gave out has been returned
+ * (agc_destroy, and the destroy call of each handle).  One of the two set
+ * without the other gives AGC_ERR_INVALID_ARG. */
+typedef void* (*agc_alloc_fn)(size_t bytes, void* user);
+typedef void (*agc_free_fn)(void* ptr, void* user);
+agc_status agc_set_allocator(agc_context* ctx, agc_alloc_fn alloc, agc_free_fn free_fn, void* user);
 agc_status agc_set_stream(agc_context* ctx, void* stream);
 /* Frees the context's workspace.  Matrices and meshes must be destroyed first. */
 agc_status agc_destroy(agc_context* ctx);

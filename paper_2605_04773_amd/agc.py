@@ -27,7 +27,7 @@ AGC_F64, AGC_F32 = 0, 1
 AGC_PREC_FP64, AGC_PREC_MIXED = 0, 1
 
 EXPORTS = (
-    "agc_create", "agc_set_stream", "agc_destroy", "agc_last_error", "agc_version",
+    "agc_create", "agc_set_stream", "agc_set_allocator", "agc_destroy", "agc_last_error", "agc_version",
     "agc_mesh_create", "agc_mesh_destroy", "agc_mesh_info", "agc_aggregate",
     "agc_assemble_coarse", "agc_assemble_fine", "agc_matrix_destroy", "agc_matrix_info",
     "agc_matrix_copy", "agc_spmv", "agc_pcg", "agc_prolongate", "agc_restrict", "agc_solve",
@@ -99,6 +99,10 @@ class agc_newton_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2605_04773_amd.build`")
@@ -108,6 +112,7 @@ def _load():
     sig = {
         "agc_create": (S, [POINTER(c_void_p), c_int32, P]),
         "agc_set_stream": (S, [P, P]),
+        "agc_set_allocator": (S, [P, ALLOC_FN, FREE_FN, P]),
         "agc_destroy": (S, [P]),
         "agc_last_error": (c_char_p, [P]),
         "agc_version": (c_char_p, []),
@@ -195,6 +200,30 @@ class Context:
         h = c_void_p()
         _check(None, _lib.agc_create(byref(h), int(device), c_void_p(s.cuda_stream)))
         self.h = h
+
+    def use_torch_allocator(self):
+        """Route the device buffers the context allocates from now on through
+        torch's caching allocator on its stream (agc_set_allocator).  Returns a
+        dict counting the blocks requested and returned."""
+        dev, stream = self.device, self.stream
+        stats = {"alloc": 0, "free": 0, "bytes": 0}
+
+        def _alloc(nbytes, _user):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            except RuntimeError:
+                return None
+            stats["alloc"] += 1
+            stats["bytes"] += int(nbytes)
+            return ptr
+
+        def _free(ptr, _user):
+            stats["free"] += 1
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_cbs = (ALLOC_FN(_alloc), FREE_FN(_free))   # kept alive with the context
+        _check(self.h, _lib.agc_set_allocator(self.h, self._alloc_cbs[0], self._alloc_cbs[1], None))
+        return stats
 
     def close(self):
         if getattr(self, "h", None):

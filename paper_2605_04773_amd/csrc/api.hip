@@ -211,6 +211,16 @@ agc_status agc_set_stream(agc_context* c, void* stream) {
   return AGC_OK;
 }
 
+agc_status agc_set_allocator(agc_context* c, agc_alloc_fn alloc, agc_free_fn free_fn, void* user) {
+  if (!c) return AGC_ERR_INVALID_ARG;
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    c->err = "alloc and free must both be set or both be null";
+    return AGC_ERR_INVALID_ARG;
+  }
+  c->alloc = agc::Allocator{alloc, free_fn, user};
+  return AGC_OK;
+}
+
 agc_status agc_destroy(agc_context* c) {
   if (!c) return AGC_ERR_INVALID_ARG;
   (void)hipSetDevice(c->device);

@@ -49,25 +49,64 @@ inline int bits_for(uint64_t maxval) {  // bits needed to represent values in [0
 
 // ----------------------------------------------------------------- workspace
 
-// Grow-only device buffer.  Reallocation calls hipFree, which waits for the
-// device, so a buffer is never released while a kernel still reads it.
+// Where device memory comes from: hipMalloc / hipFree, or a caller's pair
+// of functions (agc_set_allocator).  tl_alloc is the allocator of the
+// context whose entry point runs on this thread (set for the duration of
+// the call by API_BEGIN); null means hipMalloc.
+struct Allocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* user = nullptr;
+};
+inline thread_local const Allocator* tl_alloc = nullptr;
+struct AllocScope {
+  const Allocator* prev;
+  explicit AllocScope(const Allocator* a) : prev(tl_alloc) { tl_alloc = (a && a->alloc) ? a : nullptr; }
+  ~AllocScope() { tl_alloc = prev; }
+};
+
+// Grow-only device buffer, released through the allocator it came from.
+// With hipMalloc, reallocation calls hipFree, which waits for the device,
+// so a buffer is never released while a kernel still reads it; a caller's
+// allocator receives its blocks back in the order of the context's stream
+// (a stream-ordered caching allocator on that stream keeps the same
+// guarantee).
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  Allocator al;   // the source of p
   void* ensure(size_t bytes) {
     if (bytes <= cap && p) return p;
-    if (p) AGC_HIP(hipFree(p));
-    p = nullptr;
-    cap = 0;
-    size_t want = bytes < 256 ? 256 : bytes;
-    AGC_HIP(hipMalloc(&p, want));
+    release_or_throw();
+    const size_t want = bytes < 256 ? 256 : bytes;
+    if (tl_alloc) {
+      al = *tl_alloc;
+      p = al.alloc(want, al.user);
+      if (!p) throw Error(AGC_ERR_OUT_OF_MEMORY, "the caller's allocator returned no memory");
+    } else {
+      al = Allocator{};
+      AGC_HIP(hipMalloc(&p, want));
+    }
     cap = want;
     return p;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (al.free) al.free(p, al.user);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     cap = 0;
+    al = Allocator{};
+  }
+
+ private:
+  void release_or_throw() {
+    if (p && !al.free) AGC_HIP(hipFree(p));
+    else if (p) al.free(p, al.user);
+    p = nullptr;
+    cap = 0;
+    al = Allocator{};
   }
 };
 

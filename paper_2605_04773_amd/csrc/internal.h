@@ -191,6 +191,7 @@ struct agc_context {
   // system is large enough (the default), 0 never, 1 always; set at creation
   // from the environment variable AGC_PCG_REDUCE ("0" or "1"), for testing
   int pcg_reduce = -1;
+  agc::Allocator alloc;         // device memory source of new buffers (agc_set_allocator)
   agc::Matrix solve_a;         // matrices reused across agc_solve calls
   agc::Matrix solve_a64;
   agc::Matrix solve_fine;      // the fine system for post-coarsening
@@ -218,6 +219,7 @@ struct agc_tagger {
   if (!(ctx)) return AGC_ERR_INVALID_ARG;             \
   (ctx)->err.clear();                                 \
   try {                                               \
+    ::agc::AllocScope agc_alloc_scope_(&(ctx)->alloc);  \
     AGC_HIP(hipSetDevice((ctx)->device));
 
 #define API_END(ctx)                                  \
