@@ -143,6 +143,39 @@ def test_coarsened_loop(ctx, n, precision):
         assert abs(info.newton_iters - len(log_ref)) <= 1
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_affine_embedded_loop(ctx, precision):
+    """The paper's main variant inside the loop: aggregates of more than 8
+    vertices get 12 DoF.  It must still end at the fine loop's minimum."""
+    import torch
+    agc = binding()
+    p, d = case(ctx, 8)
+    x_t, v_t, f = synth.newton_state(p, wave_speed=0.5)
+    solve = agc.make_opts(rtol=1e-12, affine_threshold=8) if precision == "fp64" else \
+        agc.make_opts(precision=agc.AGC_PREC_MIXED, rtol=1e-7, affine_threshold=8)
+    opts = agc.make_newton_opts(eps_d=1e-4, coarsen=1, solve=solve)
+    t = lambda a: d["t"](a, torch.float64)
+    x, info = agc.agc_newton_step(ctx, d["nw"], opts, t(x_t), t(v_t), t(f))
+    mesh = {"n_verts": p["n_verts"], "rest": p["pos"], "tets": p["elem_verts"], "edges": p["edges"]}
+    _, logf = onw.time_step(mesh, synth.material(), x_t, v_t, f, eps_d=1e-4, coarsen=False)
+    e0, ef = logf[0]["energy"], logf[-1]["energy_after"]
+    log(f"[newton affine] {precision}: {info.newton_iters} iters, mean coarse size "
+        f"{info.coarse_nodes_sum / info.newton_iters:.0f}, E -> {info.energy:.10g}; fine minimum {ef:.10g}")
+    assert info.energy < info.energy0
+    assert info.energy - ef <= 1e-3 * (e0 - ef)
+    # the embedding was active: some solve had a 12-DoF node (a coarse system smaller than the fine one)
+    assert info.coarse_nodes_sum < info.newton_iters * p["n_verts"]
+    # with the threshold above every aggregate the loop is the 3-DoF one, bit for bit
+    big = agc.make_opts(rtol=1e-12, affine_threshold=10**6) if precision == "fp64" else \
+        agc.make_opts(precision=agc.AGC_PREC_MIXED, rtol=1e-7, affine_threshold=10**6)
+    plain = agc.make_opts(rtol=1e-12) if precision == "fp64" else agc.make_opts(precision=agc.AGC_PREC_MIXED, rtol=1e-7)
+    xa, ia = agc.agc_newton_step(ctx, d["nw"], agc.make_newton_opts(eps_d=1e-4, coarsen=1, solve=big), t(x_t), t(v_t),
+                                 t(f))
+    xb, ib = agc.agc_newton_step(ctx, d["nw"], agc.make_newton_opts(eps_d=1e-4, coarsen=1, solve=plain), t(x_t),
+                                 t(v_t), t(f))
+    assert torch.equal(xa, xb) and ia.newton_iters == ib.newton_iters
+
+
 def test_bad_input(ctx):
     import torch
     agc = binding()
