@@ -107,9 +107,10 @@ struct SolveResult {
   int64_t nnzb = 0;
 };
 
-// rhs_fine: the fine vector whose restriction is the right-hand side (g, or w for the adjoint)
+// rhs_fine: the fine vector whose restriction is the right-hand side (g, or w for the adjoint);
+// upper_async: the fine upper blocks are being gathered on the second stream (upper_async)
 SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_opts* o, const Restrictor& R,
-                         const double* rhs_fine, double* x_c, Timer* tm) {
+                         const double* rhs_fine, double* x_c, Timer* tm, bool upper_async = false) {
   const agc::Mesh& mesh = p->mesh->m;
   const int64_t n3c = 3 * (int64_t)R.blocks();
   SolveResult res;
@@ -121,8 +122,9 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   const bool mixed = o->precision == AGC_PREC_MIXED;
   agc::Matrix& A64 = c->solve_a64;
   agc::Matrix* A32 = mixed ? &c->solve_a : nullptr;
-  if (R.am) agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32);
-  else if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, R.n_c, AGC_F64, A64, A32);
+  if (upper_async) agc::upper_join(c);
+  if (R.am) agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32, upper_async);
+  else if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, R.n_c, AGC_F64, A64, A32, upper_async);
   else agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, A64, A32);
   res.nnzb = A64.nnzb;
   if (tm) tm->mark();
@@ -236,6 +238,12 @@ agc_status agc_destroy(agc_context* c) {
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+    (void)hipEventDestroy(c->fork);
+    (void)hipEventDestroy(c->join);
+  }
   delete c;
   return AGC_OK;
 }
@@ -503,7 +511,19 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   tm.mark();                                                   // 0
   Restrictor R{c, n, n, nullptr, nullptr, nullptr};
   int32_t* map = nullptr;
+  // The gather of the fine upper blocks needs no map: it runs on the second
+  // stream while the aggregation runs on the first.  The guard makes the
+  // context's stream wait for it on every way out of this call.
+  struct UpperGuard {
+    agc_context* c;
+    bool on = false;
+    ~UpperGuard() {
+      if (on && c->aux) (void)hipStreamWaitEvent(c->stream, c->join, 0);
+    }
+  } upper_guard{c};
   if (o->coarsen) {
+    agc::upper_async(c, mesh, p->elem_H);
+    upper_guard.on = true;
     map = map_out ? map_out : c->ws.get<int32_t>("solve.map", n);
     R.n_c = agc::aggregate(c, n, p->n_edges, p->edges, p->tags, map);
     R.map = map;
@@ -523,7 +543,7 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   }
   tm.mark();                                                   // 1
   double* x_c = R.map ? c->ws.get<double>("solve.xc", 3 * (int64_t)R.blocks()) : x;
-  SolveResult res = coarse_solve(c, p, o, R, p->g, x_c, &tm);  // marks 2 after assembly
+  SolveResult res = coarse_solve(c, p, o, R, p->g, x_c, &tm, upper_guard.on);  // marks 2 after assembly
   tm.mark();                                                   // 3
   if (R.map) {
     agc::err_reset(c);

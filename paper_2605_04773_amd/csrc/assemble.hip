@@ -302,11 +302,9 @@ void mesh_build(agc_context* c, Mesh& m, int32_t n, int64_t ne, const int32_t* e
 // plan order).
 constexpr int kGatherUnroll = 4;
 template <class In, class Acc>
-__global__ __launch_bounds__(kWG) void k_fine_gather(const In* __restrict__ eh, const uint32_t* __restrict__ pptr,
-                                                     const uint32_t* __restrict__ plan, int64_t nf,
-                                                     Acc* __restrict__ F) {
-  const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (t >= 3 * nf) return;
+__device__ __forceinline__ void fine_gather_one(const In* __restrict__ eh, const uint32_t* __restrict__ pptr,
+                                                const uint32_t* __restrict__ plan, int64_t nf, Acc* __restrict__ F,
+                                                int64_t t) {
   const int64_t f = t / 3;
   const int r = (int)(t - 3 * f);
   Acc acc[3] = {(Acc)0, (Acc)0, (Acc)0};
@@ -334,6 +332,16 @@ __global__ __launch_bounds__(kWG) void k_fine_gather(const In* __restrict__ eh, 
   }
 #pragma unroll
   for (int s = 0; s < 3; ++s) F[(int64_t)(3 * r + s) * nf + f] = acc[s];
+}
+
+// Grid-stride over (fine block, row) pairs: one pass with the full grid, or a
+// capped grid when it runs beside other work.
+template <class In, class Acc>
+__global__ __launch_bounds__(kWG) void k_fine_gather(const In* __restrict__ eh, const uint32_t* __restrict__ pptr,
+                                                     const uint32_t* __restrict__ plan, int64_t nf,
+                                                     Acc* __restrict__ F) {
+  for (int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x; t < 3 * nf; t += (int64_t)gridDim.x * kWG)
+    fine_gather_one<In, Acc>(eh, pptr, plan, nf, F, t);
 }
 
 // Full matrix values (planes of stride vs) from upper blocks U (planes of
@@ -388,6 +396,37 @@ static Acc* fine_upper(agc_context* c, const Mesh& m, const void* eh, int32_t h_
   return F;
 }
 
+// the float64 fine upper blocks left in the workspace by an earlier gather
+static double* upper_ready(agc_context* c, const Mesh& m) { return c->ws.get<double>("asm.F64", 9 * m.nf); }
+
+#ifndef AGC_ASYNC_GATHER_PER_CU
+#define AGC_ASYNC_GATHER_PER_CU 4
+#endif
+constexpr unsigned kCus = 256;
+constexpr unsigned kAsyncGatherPerCu = AGC_ASYNC_GATHER_PER_CU;
+
+void upper_async(agc_context* c, const Mesh& m, const double* elem_h) {
+  if (!c->aux) {
+    AGC_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    AGC_HIP(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    AGC_HIP(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+  }
+  double* F = upper_ready(c, m);
+  AGC_HIP(hipEventRecord(c->fork, c->stream));
+  AGC_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
+  // a capped grid (kAsyncGatherPerCu workgroups per CU) leaves CUs to the aggregation beside it
+  const unsigned full = blocks_for(3 * m.nf, kWG);
+  const unsigned grid = full < kAsyncGatherPerCu * kCus ? full : kAsyncGatherPerCu * kCus;
+  k_fine_gather<double, double><<<grid, kWG, 0, c->aux>>>(elem_h, (const uint32_t*)m.plan_ptr.p,
+                                                          (const uint32_t*)m.plan.p, m.nf, F);
+  AGC_LAUNCH_CHECK();
+  AGC_HIP(hipEventRecord(c->join, c->aux));
+}
+
+void upper_join(agc_context* c) {
+  if (c->aux) AGC_HIP(hipStreamWaitEvent(c->stream, c->join, 0));
+}
+
 // The fine matrix borrows the mesh's static pattern (no copy per assembly).
 void assemble_fine(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, int32_t out_dtype,
                    Matrix& out, Matrix* out32, bool reuse_upper) {
@@ -399,7 +438,7 @@ void assemble_fine(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtyp
   out.borrow_pattern((const int32_t*)m.ff_row_ptr.p, (const int32_t*)m.ff_col.p, (const int32_t*)m.ff_rowidx.p,
                      (const int32_t*)m.ff_diag.p);
   if (out_dtype == AGC_F64) {
-    double* F = reuse_upper ? c->ws.get<double>("asm.F64", 9 * m.nf) : fine_upper<double>(c, m, eh, h_dtype);
+    double* F = reuse_upper ? upper_ready(c, m) : fine_upper<double>(c, m, eh, h_dtype);
     float* v32 = companion32(out, out32);
     k_fill_vals<double><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>((const uint32_t*)m.ff_src.p, nnz, F, m.nf,
                                                                     (double*)out.vals.p, out.stride, v32);
@@ -476,9 +515,11 @@ struct CoarseOp {
 
 template <class Acc>
 static void coarse_impl(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, const int32_t* map,
-                        int32_t n_c, Matrix& out, Matrix* out32) {
+                        int32_t n_c, Matrix& out, Matrix* out32, bool reuse_upper) {
   const int64_t nf = m.nf;
-  Acc* F = fine_upper<Acc>(c, m, eh, h_dtype);
+  Acc* F;
+  if constexpr (sizeof(Acc) == 8) F = reuse_upper ? upper_ready(c, m) : fine_upper<Acc>(c, m, eh, h_dtype);
+  else F = fine_upper<Acc>(c, m, eh, h_dtype);
   uint64_t* k1 = c->ws.get<uint64_t>("asm.k1", nf);
   uint64_t* k2 = c->ws.get<uint64_t>("asm.k2", nf);
   uint32_t* v1 = c->ws.get<uint32_t>("asm.v1", nf);
@@ -513,11 +554,12 @@ static void coarse_impl(agc_context* c, const Mesh& m, const void* eh, int32_t h
 }
 
 void assemble_coarse(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, const int32_t* map,
-                     int32_t n_c, int32_t out_dtype, Matrix& out, Matrix* out32) {
+                     int32_t n_c, int32_t out_dtype, Matrix& out, Matrix* out32, bool reuse_upper) {
   AGC_REQUIRE(n_c >= 1 && n_c <= m.n_verts, "n_coarse out of range");
   AGC_REQUIRE(!out32 || out_dtype == AGC_F64, "a float32 companion needs a float64 matrix");
-  if (out_dtype == AGC_F64) coarse_impl<double>(c, m, eh, h_dtype, map, n_c, out, out32);
-  else coarse_impl<float>(c, m, eh, h_dtype, map, n_c, out, nullptr);
+  AGC_REQUIRE(!reuse_upper || (out_dtype == AGC_F64 && h_dtype == AGC_F64), "reused fine blocks are float64");
+  if (out_dtype == AGC_F64) coarse_impl<double>(c, m, eh, h_dtype, map, n_c, out, out32, reuse_upper);
+  else coarse_impl<float>(c, m, eh, h_dtype, map, n_c, out, nullptr, false);
 }
 
 // ------------------------------------------------ affine embedding (Eq. 4)
@@ -716,10 +758,10 @@ __global__ void k_aff_sorted(const uint64_t* __restrict__ sk, const uint32_t* __
 }
 
 void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* eh, const AffineMap& am, Matrix& out,
-                            Matrix* out32) {
+                            Matrix* out32, bool reuse_upper) {
   const int64_t nf = m.nf;
   const int32_t n_c = am.n_c, n3 = am.n3, n_flat = am.n_flat;
-  double* F = fine_upper<double>(c, m, eh, AGC_F64);
+  double* F = reuse_upper ? upper_ready(c, m) : fine_upper<double>(c, m, eh, AGC_F64);
   uint64_t* k1 = c->ws.get<uint64_t>("asm.k1", nf);
   uint64_t* k2 = c->ws.get<uint64_t>("asm.k2", nf);
   uint32_t* v1 = c->ws.get<uint32_t>("asm.v1", nf);

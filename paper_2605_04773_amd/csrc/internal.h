@@ -148,13 +148,21 @@ void mesh_build(agc_context* c, Mesh& m, int32_t n_verts, int64_t n_elems, const
 // the same element blocks left in the workspace instead of gathering them again
 void assemble_fine(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
                    int32_t out_dtype, Matrix& out, Matrix* out32 = nullptr, bool reuse_upper = false);
+// reuse_upper (float64 only): the fine upper blocks are already in the
+// workspace (upper_async + upper_join, or an assembly just before)
 void assemble_coarse(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
                      const int32_t* map, int32_t n_c, int32_t out_dtype, Matrix& out,
-                     Matrix* out32 = nullptr);
+                     Matrix* out32 = nullptr, bool reuse_upper = false);
+// The fine upper blocks of float64 element blocks gathered on the context's
+// second stream, after the work already on its stream; upper_join makes the
+// context's stream wait for them.  The gather needs no map, so it runs while
+// the aggregation does.
+void upper_async(agc_context* c, const Mesh& m, const double* elem_h);
+void upper_join(agc_context* c);
 // A = P^T H P in the flat 3-block layout of `am` (float64 sums; out32 as for
 // assemble_coarse)
 void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* elem_h, const AffineMap& am,
-                            Matrix& out, Matrix* out32 = nullptr);
+                            Matrix& out, Matrix* out32 = nullptr, bool reuse_upper = false);
 // dH_e = -(dg_e)(x_e)^T
 void elem_outer(agc_context* c, const Mesh& m, const double* dg, const double* x, double* dh);
 
@@ -192,6 +200,8 @@ struct agc_context {
   // from the environment variable AGC_PCG_REDUCE ("0" or "1"), for testing
   int pcg_reduce = -1;
   agc::Allocator alloc;         // device memory source of new buffers (agc_set_allocator)
+  hipStream_t aux = nullptr;    // second stream (default priority) for work that overlaps the main one
+  hipEvent_t fork = nullptr, join = nullptr;
   agc::Matrix solve_a;         // matrices reused across agc_solve calls
   agc::Matrix solve_a64;
   agc::Matrix solve_fine;      // the fine system for post-coarsening
