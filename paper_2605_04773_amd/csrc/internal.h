@@ -1,6 +1,9 @@
 // Internal interfaces of libagc (not part of the ABI).
 #pragma once
 
+#include <map>
+#include <tuple>
+
 #include "common.h"
 
 namespace agc {
@@ -200,6 +203,10 @@ struct agc_context {
   // from the environment variable AGC_PCG_REDUCE ("0" or "1"), for testing
   int pcg_reduce = -1;
   agc::Allocator alloc;         // device memory source of new buffers (agc_set_allocator)
+  // iterations of the last PCG solve per (rows in ~4% steps, matrix dtype,
+  // rtol in quarter decades): the first chunk of the next such solve
+  // (chunking never changes the iterates)
+  std::map<std::tuple<int32_t, int32_t, int32_t>, int32_t> pcg_last;
   hipStream_t aux = nullptr;    // second stream (default priority) for work that overlaps the main one
   hipEvent_t fork = nullptr, join = nullptr;
   agc::Matrix solve_a;         // matrices reused across agc_solve calls

@@ -777,6 +777,8 @@ __global__ __launch_bounds__(kWG) void k_pcg_check(int64_t j, const double* __re
 
 constexpr int kFirstChunk = 16;
 constexpr int kRateSpan = 8;   // iterations over which the host measures the residual's decay
+constexpr int kRepeatMargin = 3;     // extra launches when a solve repeats the last one's shape
+constexpr size_t kRepeatKeys = 64;   // remembered shapes
 static_assert(kRateSpan < kRrRing, "the ring holds the span");
 constexpr int kTimedReplays = 20;   // SpMV launches timed per PCG solve when kernel timing is on
 
@@ -841,7 +843,15 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   // convergence, though it only reads a flag, still costs the host's enqueue
   // time, while a host round trip costs that of ~5-10 iterations.
   int64_t launched = 0;
+  // a solve like the last one (rows within ~4%, same dtype, tolerance within
+  // a quarter decade) starts with a chunk of its iteration count plus a
+  // margin: usually one round trip
+  const auto key = std::make_tuple((int32_t)floor(16.0 * log2((double)n)), a.dtype,
+                                   (int32_t)floor(4.0 * log10(rtol > 0.0 ? rtol : 1e-300)));
+  const auto last = c->pcg_last.find(key);
   int chunk = kFirstChunk;
+  if (last != c->pcg_last.end() && last->second + kRepeatMargin > chunk)
+    chunk = last->second + kRepeatMargin > kMaxChunk ? kMaxChunk : last->second + kRepeatMargin;
   for (;;) {
     for (int it = 0; it < chunk; ++it) {
       const int64_t j = launched + it;
@@ -914,6 +924,10 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
     c->spmv_n += kTimedReplays;
   }
   *iters = hs->iter;
+  if (hs->done == 1) {
+    if (c->pcg_last.size() >= kRepeatKeys && !c->pcg_last.count(key)) c->pcg_last.clear();
+    c->pcg_last[key] = hs->iter;
+  }
   if (hs->bb == 0.0) {
     AGC_HIP(hipMemsetAsync(x, 0, sizeof(double) * n3, c->stream));
     *rel = 0.0;
