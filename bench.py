@@ -45,16 +45,31 @@ def spmv_bytes(nnzb, n, value_bytes):
     return nnzb * (9 * value_bytes + 4 + 4) + n * (24 + 24)
 
 
-def time_steps(fn, steps, warmup, torch):
+STEP_MS = {}
+
+
+def time_steps(fn, steps, warmup, torch, key=None):
+    """Mean ms per call over `steps` calls after `warmup`, bracketed by device
+    synchronisations.  With `key`, the per-call times (each call returns host
+    scalars, so it has synchronised its stream) are kept in STEP_MS[key]."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    last = None
+    last, marks = None, []
     for _ in range(steps):
         last = fn()
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
+    if key is not None:
+        STEP_MS[key] = np.diff(np.array([t0] + marks)) * 1e3
     return (time.perf_counter() - t0) * 1e3 / steps, last
+
+
+def spread(ms):
+    q = np.percentile(ms, [10, 50, 90])
+    return {"p10": round(float(q[0]), 4), "median": round(float(q[1]), 4), "p90": round(float(q[2]), 4),
+            "n": int(len(ms))}
 
 
 PAPER_ROW_BODIES = 96
@@ -99,7 +114,15 @@ def cpu_baseline(p, rtol):
         t0 = time.perf_counter()
         r = method.coarsened_solve(p, solver="pcg", rtol=rtol)
         ms = (time.perf_counter() - t0) * 1e3
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": round(ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "host": {"cpu": model, "os_cpu_count": os.cpu_count(),
+                     "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"), "blas_threads_used": 1},
             "sample": f"the whole workload: one coarsened solve (canonical components, sparse P^T H P, "
                       f"block-Jacobi PCG to rtol {rtol:g} in {r['iters']} iterations, prolongation), "
                       f"numpy/scipy single-threaded"}
@@ -180,8 +203,48 @@ def extras(args, p, ctx, mesh, edges, tags, ev, t, solver, extra, torch, agc, sy
     log(f"[bench] edge tags (Green strain increment, 5e-5): {ms_tag:.3f} ms, {n_prot / tag_out.numel():.3f} protected")
     extra["tag_ms_per_call"] = round(ms_tag, 4)
     extra["tag_protected_fraction"] = round(n_prot / tag_out.numel(), 4)
-    if "n_tets" not in p:   # the outer Newton loop needs a pure tetrahedral mesh
+    if "n_tets" not in p:   # the outer Newton loop and the adjoint's element blocks need a pure tetrahedral mesh
+        extra["adjoint"] = adjoint_step(args, p, ctx, mesh, edges, tags, t, torch, agc, synth)
         extra["newton"] = newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth)
+
+
+def adjoint_step(args, p, ctx, mesh, edges, tags, t, torch, agc, synth):
+    """Forward FP64 coarsened solve, then its adjoint (agc_solve_backward): per
+    call ms of each, the write rate of dL/dH_e (144 float64 per element), and
+    two identities that hold at any size for L = <w, x>: L = <dL/dg, g> and
+    sum_e <dL/dH_e, H_e> = -L (x is linear in g and homogeneous of degree -1 in H)."""
+    n_e = int(p["elem_verts"].shape[0])
+    g, eh = t(p["g"], torch.float64), t(p["elem_H"], torch.float64)
+    prob = agc.make_problem(mesh, edges, tags, eh, g, t(p["pos"], torch.float64))
+    opts = agc.make_opts(rtol=1e-12, max_iter=50000)
+    x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=g.device)
+    mp = torch.empty(p["n_verts"], dtype=torch.int32, device=g.device)
+    w = t(synth.adjoint_seed(p), torch.float64)
+    dg, dh = torch.empty_like(g), torch.empty_like(eh)
+    box = {}
+
+    def fwd():
+        box["info"] = agc.agc_solve(ctx, prob, opts, x, mp)
+        return box["info"]
+
+    def bwd():
+        return agc.agc_solve_backward(ctx, prob, opts, mp, box["info"].n_coarse, x, w, dg, dh)
+    reps = max(3, args.steps // 2)
+    ms_f, finfo = time_steps(fwd, reps, 1, torch)
+    ms_b, binfo = time_steps(bwd, reps, 1, torch)
+    L = float((w * x).sum())
+    lin = float((dg * g).sum())
+    euler = float((dh * eh).sum())
+    log(f"[bench] adjoint (FP64, rtol 1e-12): forward {ms_f:.3f} ms ({finfo.pcg_iters} iters), backward "
+        f"{ms_b:.3f} ms ({binfo.pcg_iters} iters); identities {abs(lin - L) / abs(L):.1e}, "
+        f"{abs(euler + L) / abs(L):.1e}")
+    out = {"rtol": 1e-12, "forward_ms": round(ms_f, 4), "backward_ms": round(ms_b, 4),
+           "forward_pcg_iters": finfo.pcg_iters, "backward_pcg_iters": binfo.pcg_iters,
+           "dH_bytes": n_e * 144 * 8,
+           "rel_err_linearity": abs(lin - L) / abs(L), "rel_err_homogeneity": abs(euler + L) / abs(L)}
+    del dh
+    torch.cuda.empty_cache()
+    return out
 
 
 N_DRIFT_SYSTEMS = 10
@@ -354,7 +417,7 @@ def main():
     mixed = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol)
     err_mixed = rel_err(mixed, ref_coarse)
     log("[bench] coarsened mixed-precision solve")
-    ms_mixed, info = time_steps(mixed, args.steps, args.warmup, torch)
+    ms_mixed, info = time_steps(mixed, args.steps, args.warmup, torch, key="mixed")
     log(f"[bench]   {ms_mixed:.3f} ms/solve  n_c={info.n_coarse} nnzb={info.nnzb} "
         f"pcg_iters={info.pcg_iters} refine={info.refine_iters} rel_res={info.rel_res:.2e}")
 
@@ -428,6 +491,7 @@ def main():
             "n_coarse": info.n_coarse, "nnzb_coarse": int(info.nnzb), "pcg_iters": info.pcg_iters,
             "refine_iters": info.refine_iters, "rel_res_fp64": info.rel_res, "rtol": args.rtol,
             "mesh_setup_ms": round(setup_ms, 2),
+            "step_ms": spread(STEP_MS["mixed"]),
             "phase_ms": {"aggregate": round(ph.ms_aggregate, 4), "assemble": round(ph.ms_assemble, 4),
                          "pcg": round(ph.ms_pcg, 4), "prolong": round(ph.ms_prolong, 4)},
         },
