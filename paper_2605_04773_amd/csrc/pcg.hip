@@ -339,6 +339,48 @@ __device__ __forceinline__ void row_fix(int64_t rs, int64_t re, const double* __
   }
 }
 
+// row_fix for the 64 rows of a wave at once; every lane of the wave calls it
+// (in: the lane has a row).  A row over two tiles adds its one carry on its
+// own lane, as row_fix does.  The carries of a longer (hub) row are loaded by
+// the whole wave, 64 per round, and summed across the lanes in a fixed
+// order: per lane in tile order, then by a butterfly.  Few registers are
+// live, so the rare hub row does not lower the occupancy of the caller.
+__device__ __forceinline__ void row_fix_wave(bool in, int64_t rs, int64_t re, const double* __restrict__ carry,
+                                             double q[3]) {
+  const int32_t w0 = (int32_t)(rs / kTile), w1 = (int32_t)((re - 1) / kTile);
+  if (in && re <= rs) q[0] = q[1] = q[2] = 0.0;
+  const bool split = in && re > rs && w0 != w1;
+  if (split) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) q[i] = carry[((int64_t)w0 * 2 + 1) * 3 + i];
+    if (w1 == w0 + 1) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) q[i] += carry[((int64_t)w1 * 2 + 0) * 3 + i];
+    }
+  }
+  uint64_t hub = __ballot(split && w1 > w0 + 1);
+  const int lane = (int)(threadIdx.x & 63);
+  while (hub) {
+    const int src = __ffsll((unsigned long long)hub) - 1;
+    hub &= hub - 1;
+    const int32_t a = __shfl(w0, src) + 1, b = __shfl(w1, src);
+    double h[3] = {0.0, 0.0, 0.0};
+    for (int32_t w = a + lane; w <= b; w += 64) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) h[i] += carry[((int64_t)w * 2 + 0) * 3 + i];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) h[i] += __shfl_xor(h[i], d);
+    }
+    if (lane == src) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) q[i] += h[i];
+    }
+  }
+}
+
 // q[r] for a row whose blocks may span several tiles.
 __device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const double* __restrict__ y,
                                            const double* __restrict__ carry, int64_t r, double q[3]) {
@@ -616,9 +658,28 @@ __global__ __launch_bounds__(kWG) void k_pcg_init(const double* __restrict__ b, 
   }
 }
 
+// Occupancy hints (waves per SIMD the register allocation must allow; 0 =
+// the compiler's choice) for the two per-iteration kernels.
+#ifndef AGC_SPMV_WAVES
+#define AGC_SPMV_WAVES 0
+#endif
+#ifndef AGC_UPDATE_WAVES
+#define AGC_UPDATE_WAVES 0
+#endif
+#if AGC_SPMV_WAVES > 0
+#define AGC_SPMV_OCC __attribute__((amdgpu_waves_per_eu(AGC_SPMV_WAVES)))
+#else
+#define AGC_SPMV_OCC
+#endif
+#if AGC_UPDATE_WAVES > 0
+#define AGC_UPDATE_OCC __attribute__((amdgpu_waves_per_eu(AGC_UPDATE_WAVES)))
+#else
+#define AGC_UPDATE_OCC
+#endif
+
 // K_1: w = A z, partial z^T w per tile
 template <class T>
-__global__ __launch_bounds__(kWG) void k_pcg_spmv(const int32_t* __restrict__ col, const int32_t* __restrict__ ri,
+__global__ __launch_bounds__(kWG) AGC_SPMV_OCC void k_pcg_spmv(const int32_t* __restrict__ col, const int32_t* __restrict__ ri,
                                                   const T* __restrict__ vals, int64_t nnzb, int64_t stride,
                                                   const T* __restrict__ z, double* __restrict__ w,
                                                   double* __restrict__ carry, double* __restrict__ pa,
@@ -673,7 +734,7 @@ __global__ __launch_bounds__(kWG) void k_pcg_reduce(const double* __restrict__ p
 // workgroup reads all of pb_in).  On large systems pb_in and pa are the
 // rows of k_pcg_reduce.
 template <class Z>
-__global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __restrict__ rp, int32_t n,
+__global__ __launch_bounds__(kWG) AGC_UPDATE_OCC void k_pcg_update(int64_t j, const int32_t* __restrict__ rp, int32_t n,
                                                     const double* __restrict__ wy, const double* __restrict__ carry,
                                                     const double* __restrict__ dinv, Z* __restrict__ p,
                                                     Z* __restrict__ sv, double* __restrict__ x,
@@ -717,7 +778,7 @@ __global__ __launch_bounds__(kWG) void k_pcg_update(int64_t j, const int32_t* __
   t[3] = part_finish(pa, ga, part[3]);
   wg_sum_all<4>(t, lds_a);
   if (stop_scalars(j, t, st, in_state, rtol)) return;
-  if (in) row_fix(rs, re, carry, wv);
+  row_fix_wave(in, rs, re, carry, wv);
   const double gamma = t[0];
   double beta = 0.0, den = t[3];
   if (j > 0) {

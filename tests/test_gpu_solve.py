@@ -303,3 +303,49 @@ def test_separate_partial_reduction(ctx, coarsen, precision):
     assert err <= (1e-7 if precision == "fp64" else 1e-5)
     if precision == "fp64" and coarsen:
         assert osol.relative_residual(a_c, b_c, x_r[oagg.representatives(m, nc)]) <= 1e-8
+
+
+_hub = {}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pcg_hub_rows(ctx, dtype):
+    """Two aggregates (the vertex planes k = 0 and k = 2 mod 4 of a 52^3 grid)
+    next to every singleton of the odd planes: their block rows hold ~73 K
+    blocks each, more than 64 SpMV tiles, and sit in the same wave of the
+    update kernel, whose carry sum for such rows takes several rounds.  The
+    map is given directly (assembly accepts any map).  Bar: the oracle's
+    relative residual of the PCG result <= 1e-8 (float64 matrix) and, for the
+    float32 matrix (float32 vectors r, p, s, z; rtol 1e-5) <= 1e-4: a wrong
+    carry sum of a hub row leaves a residual of order one."""
+    import torch
+    agc = binding()
+    from paper_2605_04773_amd import synth
+    if not _hub:
+        p = synth.grid_problem(52, 52, 0.6)
+        n1 = 53
+        k = np.arange(p["n_verts"]) // (n1 * n1)
+        m = np.empty(p["n_verts"], np.int64)
+        odd = k % 2 == 1
+        m[k % 4 == 0] = 0
+        m[k % 4 == 2] = 1
+        m[odd] = 2 + np.arange(int(odd.sum()))
+        nc = 2 + int(odd.sum())
+        a_c, b_c = ogal.coarse_system(p["n_verts"], p["elem_verts"], p["elem_H"], p["g"], m, nc)
+        _hub.update(p=p, m=m, nc=nc, a_c=a_c.tocsr(), b_c=b_c, d=Dev(ctx, p))
+    h = _hub
+    blocks = np.diff(h["a_c"].indptr)[[0, 3]] // 3
+    log(f"[hub] {dtype}: n_c={h['nc']}, hub rows of {blocks[0]} and {blocks[1]} blocks")
+    assert blocks.min() > 64 * 1024
+    d = h["d"]
+    mp = torch.from_numpy(h["m"].astype(np.int32)).to(ctx.device)
+    A, g_c = agc.agc_assemble_coarse(ctx, d.mesh, d.eh, d.g, mp, h["nc"],
+                                     out_dtype=agc.AGC_F64 if dtype == "f64" else agc.AGC_F32)
+    x = torch.zeros_like(g_c)
+    rtol = 1e-10 if dtype == "f64" else 1e-5
+    info = agc.agc_pcg(ctx, A, g_c, x, rtol, 20000)
+    A.close()
+    xc = x.cpu().numpy()
+    rel = osol.relative_residual(h["a_c"], h["b_c"], xc)
+    log(f"   iters={info.iters} rel_res={info.rel_res:.2e} oracle_rel={rel:.2e}")
+    assert rel <= (1e-8 if dtype == "f64" else 1e-4)
