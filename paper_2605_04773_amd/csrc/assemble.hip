@@ -17,6 +17,7 @@
 // diagonal and upper blocks, Sec. 5.2 "Overall Performance"); the lower
 // triangle is the transpose of the same sums, so A_c is exactly symmetric.
 #include <string>
+#include <vector>
 
 #include "segreduce.h"
 
@@ -232,6 +233,135 @@ static int64_t build_full(agc_context* c, int32_t n, int64_t nu, const int32_t* 
   return 2 * nu;  // upper bound; exact count = 2 nu - n_diag, read by the caller
 }
 
+// ------------------------------------------------- fine gather tables
+
+// Pieces per gather workgroup: 96 pieces of 36 float64 values are 27 KB of
+// LDS, which leaves room for five workgroups per CU.
+#ifndef AGC_GATHER_PIECES
+#define AGC_GATHER_PIECES 96
+#endif
+constexpr int kGatherPieces = AGC_GATHER_PIECES;
+// Plan entries and blocks of a workgroup: a piece of row v serves at most the
+// four blocks of row v that its element touches.
+constexpr int kGatherEntries = 4 * kGatherPieces;
+
+// deg[v] = number of elements around v: the plan length of the diagonal
+// block (v, v), the first upper block of row v (rows without elements: 0)
+__global__ void k_row_degree(const uint32_t* __restrict__ row_f0, const uint32_t* __restrict__ pptr, int32_t n,
+                             uint32_t* __restrict__ deg) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t f = row_f0[v];
+    deg[v] = f < row_f0[v + 1] ? pptr[f + 1] - pptr[f] : 0u;
+  }
+}
+
+// piece_src[piece_base[v] + s] = e*4 + a of the s-th element around v (the
+// diagonal block's plan, in element order)
+__global__ void k_piece_src(const uint32_t* __restrict__ row_f0, const uint32_t* __restrict__ pptr,
+                            const uint32_t* __restrict__ plan, const uint32_t* __restrict__ piece_base, int32_t n,
+                            uint32_t* __restrict__ src) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t g0 = piece_base[v], d = piece_base[v + 1] - g0;
+    if (d == 0) continue;
+    const uint32_t k0 = pptr[row_f0[v]];
+    for (uint32_t s = 0; s < d; ++s) src[g0 + s] = plan[k0 + s] >> 2;
+  }
+}
+
+// pentry[k] = (row_off[v] + s) * 4 + b for plan entry k = (e, a, b) of a
+// block of row v, where s is the position of e among the elements around v.
+// The plan of a block lists its elements in increasing order, a subsequence
+// of those around v, so one forward walk per block finds them; s is kept
+// below the row's degree, so every use indexes a piece of the row.
+__global__ void k_piece_entries(const int32_t* __restrict__ fu_row, const uint32_t* __restrict__ row_f0,
+                                const uint32_t* __restrict__ pptr, const uint32_t* __restrict__ plan,
+                                const uint16_t* __restrict__ row_off, int64_t nf, uint16_t* __restrict__ pentry) {
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = fu_row[f];
+    const uint32_t fd = row_f0[v];
+    const uint32_t d0 = pptr[fd], dl = pptr[fd + 1] - d0;
+    const uint32_t off = row_off[v];
+    uint32_t s = 0;
+    for (uint32_t k = pptr[f]; k < pptr[f + 1]; ++k) {
+      const uint32_t code = plan[k];
+      while (s + 1 < dl && (plan[d0 + s] >> 4) < (code >> 4)) ++s;
+      const uint32_t piece = off + s;
+      pentry[k] = (uint16_t)(((piece < 16383u ? piece : 16383u) << 2) | (code & 3u));
+    }
+  }
+}
+
+// wg_info[g] = {first piece, pieces, f0, f1, k0, k1, 0, 0} of the rows [v0, v1);
+// pieces = all ones for a run whose pieces or plan entries exceed the LDS arrays
+__global__ void k_wg_info(const int32_t* __restrict__ wg_row, int64_t n_wg, const uint32_t* __restrict__ piece_base,
+                          const uint32_t* __restrict__ row_f0, const uint32_t* __restrict__ pptr,
+                          uint32_t* __restrict__ info) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_wg; g += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v0 = wg_row[g], v1 = wg_row[g + 1];
+    const uint32_t f0 = row_f0[v0], f1 = row_f0[v1];
+    uint32_t* o = info + 8 * g;
+    const uint32_t np = piece_base[v1] - piece_base[v0];
+    const bool fits = np <= (uint32_t)kGatherPieces && pptr[f1] - pptr[f0] <= (uint32_t)kGatherEntries;
+    o[0] = piece_base[v0];
+    o[1] = fits ? np : 0xffffffffu;   // a run that does not fit reads from global memory
+    o[2] = f0;
+    o[3] = f1;
+    o[4] = pptr[f0];
+    o[5] = pptr[f1];
+    o[6] = 0;
+    o[7] = 0;
+  }
+}
+
+// Rows to gather workgroups: runs of consecutive rows whose pieces fit in
+// kGatherPieces; a row with more pieces than that has a workgroup of its own
+// (which reads from global memory instead).
+static void gather_tables(agc_context* c, Mesh& m) {
+  const int32_t n = m.n_verts;
+  uint32_t* rf = c->ws.get<uint32_t>("mesh.rowf0", n + 1);
+  uint32_t* pb = c->ws.get<uint32_t>("mesh.pbase", n + 1);
+  const uint32_t* pptr = (const uint32_t*)m.plan_ptr.p;
+  const uint32_t* plan = (const uint32_t*)m.plan.p;
+  k_key_starts<int32_t><<<grid_stride_blocks(m.nf), kWG, 0, c->stream>>>((const int32_t*)m.fu_row.p, m.nf, n, rf);
+  AGC_LAUNCH_CHECK();
+  k_row_degree<<<grid_stride_blocks(n), kWG, 0, c->stream>>>(rf, pptr, n, pb);
+  AGC_LAUNCH_CHECK();
+  scan_u32(c, pb, pb, n, "mesh.pscan");
+  uint32_t* src = (uint32_t*)m.piece_src.ensure(sizeof(uint32_t) * 4 * m.n_elems);
+  k_piece_src<<<grid_stride_blocks(n), kWG, 0, c->stream>>>(rf, pptr, plan, pb, n, src);
+  AGC_LAUNCH_CHECK();
+  std::vector<uint32_t> h(n + 1);
+  AGC_HIP(hipMemcpyAsync(h.data(), pb, sizeof(uint32_t) * (n + 1), hipMemcpyDeviceToHost, c->stream));
+  AGC_HIP(hipStreamSynchronize(c->stream));
+  AGC_REQUIRE(h[n] == 4 * (uint64_t)m.n_elems, "gather tables: piece count");
+  std::vector<int32_t> wr{0};
+  std::vector<uint16_t> off(n);
+  for (int32_t v = 0; v < n;) {
+    int32_t u = v + 1;
+    while (u < n && h[u + 1] - h[v] <= (uint32_t)kGatherPieces) ++u;
+    for (int32_t x = v; x < u; ++x) {
+      const uint32_t o = h[x] - h[v];
+      off[x] = (uint16_t)(o < 16383u ? o : 16383u);
+    }
+    wr.push_back(u);
+    v = u;
+  }
+  m.n_wg = (int64_t)wr.size() - 1;
+  int32_t* wg = c->ws.get<int32_t>("mesh.wgrow", wr.size());
+  uint16_t* offd = c->ws.get<uint16_t>("mesh.rowoff", n);
+  AGC_HIP(hipMemcpyAsync(wg, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice, c->stream));
+  AGC_HIP(hipMemcpyAsync(offd, off.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, c->stream));
+  uint32_t* info = (uint32_t*)m.wg_info.ensure(sizeof(uint32_t) * 8 * m.n_wg);
+  k_wg_info<<<grid_stride_blocks(m.n_wg), kWG, 0, c->stream>>>(wg, m.n_wg, pb, rf, pptr, info);
+  AGC_LAUNCH_CHECK();
+  uint16_t* pe = (uint16_t*)m.pentry.ensure(sizeof(uint16_t) * 10 * m.n_elems);
+  k_piece_entries<<<grid_stride_blocks(m.nf), kWG, 0, c->stream>>>((const int32_t*)m.fu_row.p, rf, pptr, plan, offd,
+                                                                    m.nf, pe);
+  AGC_LAUNCH_CHECK();
+  // the host vectors above must outlive the copies
+  AGC_HIP(hipStreamSynchronize(c->stream));
+}
+
 // ------------------------------------------------------------ mesh build
 
 void mesh_build(agc_context* c, Mesh& m, int32_t n, int64_t ne, const int32_t* ev) {
@@ -289,8 +419,7 @@ void mesh_build(agc_context* c, Mesh& m, int32_t n, int64_t ne, const int32_t* e
   AGC_HIP(hipMemcpyAsync(&nnz, fp.row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   err_throw(err_fetch(c));
   m.ff_nnzb = nnz;
-
-  AGC_HIP(hipStreamSynchronize(c->stream));
+  gather_tables(c, m);
 }
 
 // ------------------------------------------------------- per-step assembly
@@ -334,14 +463,89 @@ __device__ __forceinline__ void fine_gather_one(const In* __restrict__ eh, const
   for (int s = 0; s < 3; ++s) F[(int64_t)(3 * r + s) * nf + f] = acc[s];
 }
 
-// Grid-stride over (fine block, row) pairs: one pass with the full grid, or a
-// capped grid when it runs beside other work.
+// The gather by runs of rows (one run per workgroup, described by wg_info):
+// the workgroup copies the pieces of its rows into LDS, whole and with
+// 16-byte loads, together with its plan entries (pentry) and block offsets,
+// then forms the sums of its blocks from LDS exactly as fine_gather_one does
+// (same entries, same order, so the same bits).  A run of one row with more
+// than kGatherPieces pieces reads from global memory.  Grid-stride over the
+// runs: one pass with the full grid, or a capped grid when it runs beside
+// other work.  staged = 0 (element blocks not 16-byte aligned): every run
+// reads from global memory.
 template <class In, class Acc>
 __global__ __launch_bounds__(kWG) void k_fine_gather(const In* __restrict__ eh, const uint32_t* __restrict__ pptr,
-                                                     const uint32_t* __restrict__ plan, int64_t nf,
-                                                     Acc* __restrict__ F) {
-  for (int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x; t < 3 * nf; t += (int64_t)gridDim.x * kWG)
-    fine_gather_one<In, Acc>(eh, pptr, plan, nf, F, t);
+                                                     const uint32_t* __restrict__ plan,
+                                                     const uint16_t* __restrict__ pentry,
+                                                     const uint32_t* __restrict__ piece_src,
+                                                     const uint4* __restrict__ wg_info, int64_t n_wg, int64_t nf,
+                                                     Acc* __restrict__ F, int staged) {
+  constexpr int kPieceVals = 36;
+  constexpr int kChunks = kPieceVals * (int)sizeof(In) / 16;   // 16-byte chunks per piece
+  constexpr int kFill = (kGatherPieces * kChunks + kWG - 1) / kWG;
+  __shared__ __align__(16) In lds[kGatherPieces * kPieceVals];
+  __shared__ uint16_t le[kGatherEntries];       // plan entries of the run, from k0
+  __shared__ uint16_t lp[kGatherEntries + 1];   // plan offsets of its blocks, from f0
+  for (int64_t g = blockIdx.x; g < n_wg; g += gridDim.x) {
+    const uint4 wa = wg_info[2 * g], wb = wg_info[2 * g + 1];
+    const uint32_t p0 = wa.x, np = wa.y, f0 = wa.z, f1 = wa.w, k0 = wb.x, k1 = wb.y;
+    if (!staged || np > (uint32_t)kGatherPieces) {   // the same for the whole workgroup
+      for (int64_t t = 3 * (int64_t)f0 + threadIdx.x; t < 3 * (int64_t)f1; t += kWG)
+        fine_gather_one<In, Acc>(eh, pptr, plan, nf, F, t);
+      continue;
+    }
+    if (np == 0) continue;   // rows without elements: no blocks
+    const uint32_t nc = np * kChunks, ne = k1 - k0, nb = f1 - f0;
+    // Branch-free loads (indices past the end repeat the last one), all
+    // issued before the first store: the piece sources, then the pieces,
+    // the entries and the block offsets.
+    constexpr int kE = (kGatherEntries + kWG - 1) / kWG, kB = (kGatherEntries + 1 + kWG - 1) / kWG;
+    uint32_t srcs[kFill];
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const uint32_t cidx = min(threadIdx.x + u * kWG, nc - 1);
+      srcs[u] = piece_src[p0 + cidx / kChunks];
+    }
+    uint16_t ev[kE];
+    uint32_t bv[kB];
+#pragma unroll
+    for (int u = 0; u < kE; ++u) ev[u] = pentry[k0 + min(threadIdx.x + u * kWG, ne - 1)];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) bv[u] = pptr[f0 + min(threadIdx.x + u * kWG, nb)];
+    uint4 buf[kFill];
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const uint32_t cidx = min(threadIdx.x + u * kWG, nc - 1);
+      const uint32_t q = cidx - (cidx / kChunks) * kChunks;
+      buf[u] = reinterpret_cast<const uint4*>(eh + (int64_t)(srcs[u] >> 2) * 144 + kPieceVals * (srcs[u] & 3))[q];
+    }
+    // the stores use the same clamped indices (a repeated index stores the
+    // value its owner stores), so no store is conditional and the loads
+    // above stay in flight together
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kE; ++u) le[min(threadIdx.x + u * kWG, ne - 1)] = ev[u];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) lp[min(threadIdx.x + u * kWG, nb)] = (uint16_t)(bv[u] - k0);
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) reinterpret_cast<uint4*>(lds)[min(threadIdx.x + u * kWG, nc - 1)] = buf[u];
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < 3 * nb; t += kWG) {
+      const uint32_t fl = t / 3;
+      const int r = (int)(t - 3 * fl);
+      Acc acc[3] = {(Acc)0, (Acc)0, (Acc)0};
+      const uint32_t e1 = lp[fl + 1];
+      for (uint32_t e = lp[fl]; e < e1; ++e) {
+        const uint32_t pe = le[e];
+        const In* pv = lds + (pe >> 2) * kPieceVals + 12 * r + 3 * (pe & 3u);
+#pragma unroll
+        for (int sx = 0; sx < 3; ++sx) acc[sx] += (Acc)pv[sx];
+      }
+      const int64_t f = (int64_t)f0 + fl;
+#pragma unroll
+      for (int sx = 0; sx < 3; ++sx) F[(int64_t)(3 * r + sx) * nf + f] = acc[sx];
+    }
+    __syncthreads();   // the next run refills the shared arrays
+  }
 }
 
 // Full matrix values (planes of stride vs) from upper blocks U (planes of
@@ -382,10 +586,18 @@ static float* companion32(const Matrix& a, Matrix* out32) {
 }
 
 template <class In, class Acc>
-static void gather_fine(agc_context* c, const Mesh& m, const void* eh, Acc* F) {
-  k_fine_gather<In, Acc><<<blocks_for(3 * m.nf, kWG), kWG, 0, c->stream>>>(
-      (const In*)eh, (const uint32_t*)m.plan_ptr.p, (const uint32_t*)m.plan.p, m.nf, F);
+static void launch_gather(agc_context* c, const Mesh& m, const In* eh, Acc* F, hipStream_t st, unsigned grid) {
+  // the pieces are copied with 16-byte loads
+  const int staged = ((uintptr_t)eh & 15u) == 0 ? 1 : 0;
+  k_fine_gather<In, Acc><<<grid, kWG, 0, st>>>(
+      eh, (const uint32_t*)m.plan_ptr.p, (const uint32_t*)m.plan.p, (const uint16_t*)m.pentry.p,
+      (const uint32_t*)m.piece_src.p, (const uint4*)m.wg_info.p, m.n_wg, m.nf, F, staged);
   AGC_LAUNCH_CHECK();
+}
+
+template <class In, class Acc>
+static void gather_fine(agc_context* c, const Mesh& m, const void* eh, Acc* F) {
+  launch_gather<In, Acc>(c, m, (const In*)eh, F, c->stream, (unsigned)m.n_wg);
 }
 
 template <class Acc>
@@ -415,11 +627,9 @@ void upper_async(agc_context* c, const Mesh& m, const double* elem_h) {
   AGC_HIP(hipEventRecord(c->fork, c->stream));
   AGC_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
   // a capped grid (kAsyncGatherPerCu workgroups per CU) leaves CUs to the aggregation beside it
-  const unsigned full = blocks_for(3 * m.nf, kWG);
+  const unsigned full = (unsigned)m.n_wg;
   const unsigned grid = full < kAsyncGatherPerCu * kCus ? full : kAsyncGatherPerCu * kCus;
-  k_fine_gather<double, double><<<grid, kWG, 0, c->aux>>>(elem_h, (const uint32_t*)m.plan_ptr.p,
-                                                          (const uint32_t*)m.plan.p, m.nf, F);
-  AGC_LAUNCH_CHECK();
+  launch_gather<double, double>(c, m, elem_h, F, c->aux, grid);
   AGC_HIP(hipEventRecord(c->join, c->aux));
 }
 

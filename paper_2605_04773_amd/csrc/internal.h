@@ -72,9 +72,17 @@ struct Mesh {
   // full fine pattern from the upper one
   int64_t ff_nnzb = 0;
   DevBuf ff_row_ptr, ff_col, ff_rowidx, ff_src, ff_diag;   // src = upper*2 + transposed
+  // Tables of the fine gather.  A piece is rows 3a..3a+2 of an element
+  // block, a the local index of a vertex v of the element: the upper blocks
+  // of row v read only the pieces of the elements around v.
+  DevBuf piece_src;      // [4 n_elems] e*4 + a of each piece, rows in order, elements in order
+  DevBuf pentry;         // [10 n_elems] u16: plan entry k as (piece within its workgroup) * 4 + b
+  DevBuf wg_info;        // [n_wg][8] u32 per gather workgroup: first piece, pieces, blocks [f0, f1), plan [k0, k1)
+  int64_t n_wg = 0;
   void release() {
     elem_verts.release(); fu_row.release(); fu_col.release(); plan_ptr.release(); plan.release();
     ff_row_ptr.release(); ff_col.release(); ff_rowidx.release(); ff_src.release(); ff_diag.release();
+    piece_src.release(); pentry.release(); wg_info.release();
   }
 };
 

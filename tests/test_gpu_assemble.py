@@ -178,3 +178,47 @@ def test_mesh_rejects_bad_elements(ctx):
     ev = torch.tensor([[0, 1, 2, 4]], dtype=torch.int32, device=ctx.device)
     with pytest.raises(agc.BadInput):
         agc.agc_mesh_create(ctx, 4, ev)
+
+
+@pytest.mark.parametrize("h_dtype", ["f64", "f32"])
+def test_fine_gather_paths_agree(ctx, h_dtype):
+    """The fine gather stages the element blocks around each row in LDS; a
+    row around more elements than fit, and element blocks that are not
+    16-byte aligned, are gathered from global memory instead.  Here one
+    vertex lies in 300 tetrahedra (a row over the limit) and the others in a
+    few: the sums match the oracle's to rounding, and the aligned (staged)
+    and misaligned (global) calls agree bit for bit."""
+    import torch
+    agc = binding()
+    rng = np.random.default_rng(11)
+    k, nv = 300, 201
+    ev = np.empty((k, 4), np.int64)
+    ev[:, 0] = 0
+    for e in range(k):   # every other vertex in 4 or 5 elements
+        ev[e, 1:] = 1 + (3 * e + np.arange(3)) % (nv - 1)
+    a = rng.standard_normal((k, 12, 12))
+    eh = (a + np.swapaxes(a, 1, 2)).reshape(k, 144)
+    tdt = torch.float64 if h_dtype == "f64" else torch.float32
+    if h_dtype == "f32":
+        eh = eh.astype(np.float32).astype(np.float64)   # the values the float32 call sees
+    mesh = agc.agc_mesh_create(ctx, nv, torch.from_numpy(ev.astype(np.int32)).to(ctx.device))
+    aligned = torch.from_numpy(eh).to(ctx.device, tdt)
+    flat = torch.zeros(k * 144 + 1, dtype=tdt, device=ctx.device)
+    flat[1:] = aligned.reshape(-1)
+    shifted = flat[1:].view(k, 144)
+    assert aligned.data_ptr() % 16 == 0 and shifted.data_ptr() % 16 != 0
+    h1 = agc.agc_assemble_fine(ctx, mesh, aligned)
+    h2 = agc.agc_assemble_fine(ctx, mesh, shifted)
+    rp, ci, vals = bsr_numpy(h1)
+    rp2, ci2, vals2 = bsr_numpy(h2)
+    assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2) and np.array_equal(vals, vals2)
+    ident = np.arange(nv)
+    pr, pc = ogal.coarse_pattern(ev, ident, nv)
+    assert np.array_equal(ci, pc)
+    ref = ogal.to_blocks(ogal.fine_hessian(nv, ev, eh), pr, pc)
+    ab = ogal.to_blocks(ogal.fine_hessian(nv, ev, np.abs(eh)), pr, pc)
+    log(f"[asm] gather paths {h_dtype}: row 0 sums {np.diff(rp)[0]} blocks of up to {k} sub-blocks")
+    assert (np.abs(vals - ref) <= 2 * gamma(k + 16) * ab).all()
+    h1.close()
+    h2.close()
+    mesh.close()
