@@ -91,11 +91,12 @@ __device__ __forceinline__ void load_items(const T* p, T (&o)[kItems]) {
 // preconditioned vector of the float32-matrix PCG).
 template <class V>
 struct Gather {
+  using E = V;   // gathered values stay in the vector's type until used
   const V* x;
-  __device__ __forceinline__ void get(int64_t c, double o[3]) const {
-    o[0] = (double)x[3 * c];
-    o[1] = (double)x[3 * c + 1];
-    o[2] = (double)x[3 * c + 2];
+  __device__ __forceinline__ void get(int64_t c, V o[3]) const {
+    o[0] = x[3 * c];
+    o[1] = x[3 * c + 1];
+    o[2] = x[3 * c + 2];
   }
 };
 using GatherX = Gather<double>;
@@ -187,14 +188,15 @@ __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G
   const unsigned lane = lane_id(), wave = threadIdx.x / kWave;
   double v[kItems][3];
   double dot = 0.0;
-  double pr0[3] = {0.0, 0.0, 0.0}, pr3[3] = {0.0, 0.0, 0.0};
+  using E = typename G::E;
+  E pr0[3] = {E(0), E(0), E(0)}, pr3[3] = {E(0), E(0), E(0)};
   if (DOT) {   // gathered unconditionally (a masked row reads entry 0), with the columns
     const int32_t r0 = q.r[0] != INT32_MAX ? q.r[0] : 0;
     const int32_t r3 = q.r[kItems - 1] != INT32_MAX ? q.r[kItems - 1] : r0;
     g.get(r0, pr0);
     g.get(r3, pr3);
   }
-  double xg[kItems][3];
+  E xg[kItems][3];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) g.get(q.c[j], xg[j]);
   // all gathers are in flight before any product is formed: left to itself
@@ -202,7 +204,7 @@ __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    const double* xv = xg[j];
+    const double xv[3] = {(double)xg[j][0], (double)xg[j][1], (double)xg[j][2]};
     const bool in = q.r[j] != INT32_MAX;   // a masked block's values may be padding
     const double v0 = (double)q.a[0][j] * xv[0] + (double)q.a[1][j] * xv[1] + (double)q.a[2][j] * xv[2];
     const double v1 = (double)q.a[3][j] * xv[0] + (double)q.a[4][j] * xv[1] + (double)q.a[5][j] * xv[2];
@@ -216,7 +218,7 @@ __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G
     for (int j = 0; j < kItems; ++j) {
       const int32_t rj = q.r[j];
       if (rj == INT32_MAX) continue;
-      double pr[3];
+      E pr[3];
       if (rj == q.r[0]) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) pr[i] = pr0[i];
@@ -226,7 +228,7 @@ __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G
       } else {
         g.get(rj, pr);
       }
-      dot += pr[0] * v[j][0] + pr[1] * v[j][1] + pr[2] * v[j][2];
+      dot += (double)pr[0] * v[j][0] + (double)pr[1] * v[j][1] + (double)pr[2] * v[j][2];
     }
   }
   // the thread's last run, scanned across the wave, then across waves
