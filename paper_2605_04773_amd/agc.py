@@ -462,7 +462,12 @@ def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None) -> agc_problem:
     _dev(g, torch.float64, (mesh.n_verts, 3), "g", ctx.device)
     if rest is not None:
         _dev(rest, torch.float64, (mesh.n_verts, 3), "rest", ctx.device)
-    return agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g), _ptr(rest))
+    prob = agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g), _ptr(rest))
+    # The struct holds raw device pointers that every later call reads: it
+    # keeps the tensors (and the mesh) alive, or a temporary passed here would
+    # be freed and its memory handed to the next allocation of that size.
+    prob._keep = (mesh, edges, tags, elem_H, g, rest)
+    return prob
 
 
 def agc_solve(ctx: Context, prob: agc_problem, opts: agc_solve_opts, x: torch.Tensor, map_out=None):

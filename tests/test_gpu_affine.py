@@ -160,3 +160,26 @@ def test_affine_needs_rest_and_no_backward(ctx):
         agc.agc_solve(ctx, prob, agc.make_opts(affine_threshold=THR), x, None)
     with pytest.raises(agc.AgcError):
         agc.agc_solve_backward(ctx, d.problem(), agc.make_opts(affine_threshold=THR), None, 0, None, None, None, None)
+
+
+def test_problem_keeps_its_tensors(ctx):
+    """The problem struct holds device pointers that agc_solve reads later:
+    make_problem keeps the tensors alive.  Here the rest positions are a
+    temporary, and the next allocation of their size (zeros, then the
+    output) would otherwise take their memory, which makes every affine
+    frame coordinate zero and the coarse matrix singular."""
+    import gc
+    import torch
+    agc = binding()
+    d = dev(ctx, "c4")
+    p = d.p
+    prob = agc.make_problem(d.mesh, d.edges, d.tags, d.eh, d.g, d.rest.clone())
+    gc.collect()
+    zeros = torch.zeros((p["n_verts"], 3), dtype=torch.float64, device=ctx.device)
+    x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=ctx.device)
+    info = agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-10, max_iter=50000, affine_threshold=THR), x, None)
+    _, cls, _, _, _, x_ref = _affine_reference(p, THR)
+    err = np.linalg.norm(x.cpu().numpy() - x_ref) / np.linalg.norm(x_ref)
+    log(f"[aff] temporary rest: n12={info.n_affine} iters={info.pcg_iters} err={err:.2e}")
+    assert info.n_affine == cls["n12"] >= 1 and err <= 1e-7
+    del zeros
