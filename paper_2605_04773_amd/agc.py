@@ -276,8 +276,10 @@ class Tagger:
 
 
 class Matrix:
-    def __init__(self, ctx: Context, h):
-        self.ctx, self.h = ctx, h
+    def __init__(self, ctx: Context, h, keep=None):
+        # keep: an object whose device memory the matrix uses (the mesh, whose
+        # static pattern a fine matrix borrows), kept alive with it
+        self.ctx, self.h, self._keep = ctx, h, keep
         n, nnzb, dt = c_int32(), c_int64(), c_int32()
         _lib.agc_matrix_info(h, byref(n), byref(nnzb), byref(dt))
         self.n_rows, self.nnzb, self.dtype = n.value, nnzb.value, dt.value
@@ -396,7 +398,7 @@ def agc_assemble_fine(ctx: Context, mesh: Mesh, elem_H: torch.Tensor, out_dtype:
     _dev(elem_H, elem_H.dtype, (mesh.n_elems, 144), "elem_H", ctx.device)
     h = c_void_p()
     _check(ctx.h, _lib.agc_assemble_fine(ctx.h, mesh.h, _ptr(elem_H), _h_dtype(elem_H), int(out_dtype), byref(h)))
-    return Matrix(ctx, h)
+    return Matrix(ctx, h, keep=mesh)
 
 
 def agc_spmv(ctx: Context, A: Matrix, x: torch.Tensor, y=None) -> torch.Tensor:
@@ -479,8 +481,9 @@ def agc_solve(ctx: Context, prob: agc_problem, opts: agc_solve_opts, x: torch.Te
 class Newton:
     """One implicit time step's Newton loop on the tetrahedra of a mesh (agc_newton_*)."""
 
-    def __init__(self, ctx: Context, h, n_verts, n_elems):
-        self.ctx, self.h, self.n_verts, self.n_elems = ctx, h, n_verts, n_elems
+    def __init__(self, ctx: Context, h, n_verts, n_elems, mesh=None):
+        # the handle uses the mesh's static structure: the mesh is kept alive with it
+        self.ctx, self.h, self.n_verts, self.n_elems, self.mesh = ctx, h, n_verts, n_elems, mesh
 
     def close(self):
         if getattr(self, "h", None) and self.ctx.h:
@@ -502,7 +505,7 @@ def agc_newton_create(ctx: Context, mesh: Mesh, edges: torch.Tensor, rest: torch
     mat = agc_material(float(mu), float(lam), float(rho), float(h))
     out = c_void_p()
     _check(ctx.h, _lib.agc_newton_create(ctx.h, mesh.h, int(m), _ptr(edges), _ptr(rest), byref(mat), byref(out)))
-    return Newton(ctx, out, mesh.n_verts, mesh.n_elems)
+    return Newton(ctx, out, mesh.n_verts, mesh.n_elems, mesh)
 
 
 def make_newton_opts(max_newton=50, eps_d=1e-3, tag_threshold=5e-5, coarsen=1, solve=None) -> agc_newton_opts:

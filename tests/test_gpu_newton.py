@@ -194,3 +194,25 @@ def test_bad_input(ctx):
     # the handle still works
     x, info = agc.agc_newton_step(ctx, d["nw"], agc.make_newton_opts(eps_d=1e-3), t(x_t), t(v_t), None)
     assert info.newton_iters >= 1 and info.energy < info.energy0
+
+
+def test_handle_keeps_its_mesh(ctx):
+    """The Newton handle uses its mesh's static structure: the binding keeps
+    the mesh alive while only the handle refers to it (a collected mesh
+    would be destroyed under the handle)."""
+    import gc
+    import torch
+    agc = binding()
+    p = synth.grid_problem(3, 77, 0.6)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(ctx.device, dt)
+    m = synth.material()
+    nw = agc.agc_newton_create(ctx, agc.agc_mesh_create(ctx, p["n_verts"], t(p["elem_verts"], torch.int32)),
+                               t(p["edges"], torch.int32), t(p["pos"], torch.float64), m["mu"], m["lam"], m["rho"],
+                               m["h"])
+    gc.collect()
+    assert nw.mesh is not None and nw.mesh.h is not None
+    x_t, v_t, f = synth.newton_state(p, wave_speed=0.5)
+    x, info = agc.agc_newton_step(ctx, nw, agc.make_newton_opts(eps_d=1e-3), t(x_t, torch.float64),
+                                  t(v_t, torch.float64), t(f, torch.float64))
+    assert info.newton_iters >= 1 and info.energy < info.energy0
+    nw.close()
