@@ -254,6 +254,9 @@ agc_status agc_restrict(agc_context* ctx, int32_t n_verts, const int32_t* map,
 
 /* ----------------------------------------------------------- all in one */
 
+/* The arrays a problem points to are read during each call that takes the
+ * problem (agc_solve, agc_solve_backward) and are not kept after it; the
+ * caller keeps them valid and unchanged for the duration of those calls. */
 typedef struct {
   const agc_mesh* mesh;    /* from agc_mesh_create                             */
   int64_t n_edges;         /* edge list for the aggregation                    */
