@@ -127,3 +127,55 @@ def check_adjoint_identities(L, g, dg, elem_H, dH, rtol=1e-10):
     assert abs(lin - L) <= rtol * max(abs(L), np.abs(dg * g).sum()), (lin, L)
     euler = float(np.sum(np.asarray(dH).reshape(-1) * np.asarray(elem_H).reshape(-1)))
     assert abs(euler + L) <= rtol * max(abs(L), np.abs(np.asarray(dH).reshape(-1) * np.asarray(elem_H).reshape(-1)).sum()), (euler, L)
+
+
+# --------------------------------------------------------------- affine order
+
+def supplement_node_order(sizes, threshold):
+    """Node order and flat 3-block offsets built from the supplement's Alg. 3
+    and its index formulas, without the oracle.
+
+    Alg. 3: a node with more than ``threshold`` members is a 12-DoF node and
+    gets the sort key i + n_c, any other node the key i; a pair sort of
+    (key, node index) puts the 3-DoF nodes first, each kind in label order;
+    a node's new label is its position in that sorted order.  The row index
+    formula of the supplement (Sec. 2, after Alg. 4) places sub-block K of a
+    12-DoF node at r = n3 + (new - n3) * 4 + floor(K / 4) and its column at
+    c = n3 + (new - n3) * 4 + K % 4; a 3-DoF node's global index is its new
+    label.  Returns (new_label, offset, n3) with offset the first flat
+    3-block of every node."""
+    sizes = np.asarray(sizes)
+    n_c = sizes.shape[0]
+    keys = [i + n_c if sizes[i] > threshold else i for i in range(n_c)]
+    indices = sorted(range(n_c), key=lambda i: keys[i])      # the SortPairs step (keys are distinct)
+    new_label = [0] * n_c
+    for pos, i in enumerate(indices):
+        new_label[i] = pos
+    n3 = sum(1 for i in range(n_c) if sizes[i] <= threshold)
+    offset = []
+    for i in range(n_c):
+        if sizes[i] > threshold:
+            rows = {n3 + (new_label[i] - n3) * 4 + K // 4 for K in range(16)}
+            cols = {n3 + (new_label[i] - n3) * 4 + K % 4 for K in range(16)}
+            assert rows == cols and len(rows) == 4
+            offset.append(min(rows))
+        else:
+            offset.append(new_label[i])
+    return np.array(new_label), np.array(offset), n3
+
+
+def check_affine_order(classify, map_, n_c, threshold):
+    """classify(map, n_c, threshold)['new_label' / 'offset' / 'n3'] follow Alg. 3
+    and the supplement's index formulas; the flat 3-blocks tile [0, n3 + 4 n12)."""
+    sizes = np.bincount(np.asarray(map_, dtype=np.int64), minlength=n_c)
+    want_lab, want_off, want_n3 = supplement_node_order(sizes, threshold)
+    cls = classify(np.asarray(map_), n_c, threshold)
+    assert int(cls["n3"]) == want_n3, "3-DoF node count"
+    assert np.array_equal(np.asarray(cls["new_label"]), want_lab), "node order differs from Alg. 3"
+    assert np.array_equal(np.asarray(cls["offset"]), want_off), "flat offsets differ from the index formulas"
+    big = sizes > threshold
+    width = np.where(big, 4, 1)
+    cover = np.zeros(want_n3 + 4 * int(big.sum()), np.int64)
+    for c in range(n_c):
+        cover[want_off[c]: want_off[c] + width[c]] += 1
+    assert (cover == 1).all(), "flat 3-blocks overlap or leave gaps"

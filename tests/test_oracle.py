@@ -453,3 +453,28 @@ def test_affine_mutants_trip_the_pins():
     v2 = vals.copy()
     v2[sel3] = 0.0
     assert not moments_ok(sp.csr_matrix((v2, (rows, cols)), shape=good.shape))
+
+
+def _interleaved_affine_map():
+    """A hand-made map whose 12-DoF nodes (more than 4 members) sit at low,
+    middle and high labels between 3-DoF nodes: sizes by label 6, 1, 2, 5, 1, 9, 3, 1, 7."""
+    sizes = [6, 1, 2, 5, 1, 9, 3, 1, 7]
+    return np.repeat(np.arange(len(sizes)), sizes).astype(np.int32), len(sizes), 4
+
+
+def test_affine_node_order_follows_alg3():
+    """The oracle's node classification and flat offsets equal those built from
+    the supplement's Alg. 3 (sort keys i and i + n_c) and its row/column index
+    formulas, on a map where 12-DoF nodes carry labels below 3-DoF ones, and
+    on the 8^3 grid's map with thresholds that make one or several 12-DoF nodes."""
+    from oracle import affine
+    m, n_c, thr = _interleaved_affine_map()
+    pins.check_affine_order(affine.classify, m, n_c, thr)
+    cls = affine.classify(m, n_c, thr)
+    # written out for this map: 3-DoF labels 1, 2, 4, 6, 7 -> 0..4; 12-DoF 0, 3, 5, 8 -> 5..8
+    assert cls["new_label"].tolist() == [5, 0, 1, 6, 2, 7, 3, 4, 8]
+    assert cls["offset"].tolist() == [5, 0, 1, 9, 2, 13, 3, 4, 17]
+    p = synth.make_config("c1")
+    mg, ncg = aggregate.components(p["n_verts"], p["edges"], p["tags"])
+    for thr in (1, 3, 32):
+        pins.check_affine_order(affine.classify, mg, ncg, thr)

@@ -134,3 +134,39 @@ def test_mutant_pcg_wrong_beta(c1):
         p = z + (rz / rz_new) * p
         rz = rz_new
     assert np.linalg.norm(x - x_star) > 1e-8 * np.linalg.norm(x_star)
+
+
+def test_mutants_affine_node_order():
+    """Three plausible slips in the affine node order each trip the Alg. 3 pin:
+    12-DoF nodes first; no reorder at all (offsets by canonical label); and
+    12-DoF nodes in reverse label order."""
+    from oracle import affine
+    m = np.repeat(np.arange(9), [6, 1, 2, 5, 1, 9, 3, 1, 7]).astype(np.int32)
+    n_c, thr = 9, 4
+
+    def twelve_first(map_, n, t):
+        big = np.bincount(map_, minlength=n) > t
+        n12 = int(big.sum())
+        lab = np.empty(n, np.int64)
+        lab[big] = np.arange(n12)
+        lab[~big] = n12 + np.arange(n - n12)
+        off = np.where(big, 4 * lab, 4 * n12 + (lab - n12))
+        return {"new_label": lab, "offset": off, "n3": n - n12}
+
+    def no_reorder(map_, n, t):
+        big = np.bincount(map_, minlength=n) > t
+        width = np.where(big, 4, 1)
+        off = np.concatenate([[0], np.cumsum(width)[:-1]])
+        return {"new_label": np.arange(n), "offset": off, "n3": int((~big).sum())}
+
+    def reversed_12(map_, n, t):
+        cls = affine.classify(map_, n, t)
+        big = cls["big"]
+        lab = cls["new_label"].copy()
+        lab[big] = lab[big][::-1]
+        off = np.where(big, cls["n3"] + 4 * (lab - cls["n3"]), lab)
+        return {"new_label": lab, "offset": off, "n3": cls["n3"]}
+
+    pins.check_affine_order(affine.classify, m, n_c, thr)
+    for mutant in (twelve_first, no_reorder, reversed_12):
+        assert _fails(pins.check_affine_order, mutant, m, n_c, thr), mutant.__name__
