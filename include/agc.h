@@ -237,8 +237,14 @@ typedef struct {
  * definite.  x holds the initial guess on entry (zeros for the standard
  * start) and the result on exit.  Stops when the recurrence residual
  * satisfies ||r||_2 <= rtol ||b||_2 or after max_iter iterations
- * (AGC_ERR_NOT_CONVERGED, x = last iterate).  Vectors and inner products are
- * float64 for both matrix dtypes.  info may be NULL.  Synchronises. */
+ * (AGC_ERR_NOT_CONVERGED, x = last iterate).  x, the product A z and every
+ * inner product are float64.  The recurrence vectors r, z = D^{-1} r, p and
+ * s = A p are stored in the matrix's value type: float64 for a float64
+ * matrix; for a float32 matrix each is rounded to float32 once per update
+ * and used as stored, so the residual behind the stop test and rel_res is
+ * that float32 recurrence (its float64 true residual can differ by about the
+ * float32 rounding of A x, relative to ||b||).  info may be NULL.
+ * Synchronises. */
 agc_status agc_pcg(agc_context* ctx, const agc_matrix* A, const double* b, double* x,
                    double rtol, int32_t max_iter, agc_pcg_info* info);
 
@@ -248,7 +254,9 @@ agc_status agc_pcg(agc_context* ctx, const agc_matrix* A, const double* b, doubl
 agc_status agc_prolongate(agc_context* ctx, int32_t n_verts, const int32_t* map,
                           int32_t n_coarse, const double* x_c, double* x);
 /* v_c = P^T v: v_c[c] = sum of v over the members of c, summed in a fixed
- * order (Sec. 4.1, g_c = sum over child(c) of g_f). */
+ * order (Sec. 4.1, g_c = sum over child(c) of g_f).  Every label in
+ * [0, n_coarse) must have a member (as agc_aggregate's maps do):
+ * AGC_ERR_BAD_INPUT for a map value out of range or a label without members. */
 agc_status agc_restrict(agc_context* ctx, int32_t n_verts, const int32_t* map,
                         int32_t n_coarse, const double* v, double* v_c);
 
@@ -320,7 +328,11 @@ typedef struct {
  * coarse assembly, coarse solve, prolongation): x = P A_c^{-1} P^T g.
  *   x       : [n_verts][3] float64 out.
  *   map_out : [n_verts] int32 out, may be NULL.
- *   info    : [host] out, may be NULL.  Synchronises. */
+ *   info    : [host] out, may be NULL.  Synchronises.
+ * When the coarse PCG stops at max_iter (or the mixed refinement at
+ * max_refine) before rtol, the remaining steps still run on the last coarse
+ * iterate x_c: x = P x_c (then post-coarsening, if asked), info is filled,
+ * and the call returns AGC_ERR_NOT_CONVERGED. */
 agc_status agc_solve(agc_context* ctx, const agc_problem* prob, const agc_solve_opts* opts,
                      double* x, int32_t* map_out, agc_solve_info* info);
 
@@ -331,7 +343,10 @@ agc_status agc_solve(agc_context* ctx, const agc_problem* prob, const agc_solve_
  * again, never stored.  dg: [n_verts][3] float64 out; dH: [n_elems][144]
  * float64 out, may be NULL.  opts->precision selects the solve as in
  * agc_solve; opts->post_iters and opts->affine_threshold must be 0 (the
- * derivative is that of the 3-DoF coarsened solve).  Synchronises. */
+ * derivative is that of the 3-DoF coarsened solve).  The map must use every
+ * label in [0, n_coarse) (AGC_ERR_BAD_INPUT otherwise).  A PCG stopped at
+ * max_iter (or max_refine) still gives dg and dH from its last iterate, with
+ * AGC_ERR_NOT_CONVERGED.  Synchronises. */
 agc_status agc_solve_backward(agc_context* ctx, const agc_problem* prob,
                               const agc_solve_opts* opts, const int32_t* map, int32_t n_coarse,
                               const double* x, const double* w, double* dg, double* dH,

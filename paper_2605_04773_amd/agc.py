@@ -472,9 +472,16 @@ def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None) -> agc_problem:
     return prob
 
 
-def agc_solve(ctx: Context, prob: agc_problem, opts: agc_solve_opts, x: torch.Tensor, map_out=None):
+def agc_solve(ctx: Context, prob: agc_problem, opts: agc_solve_opts, x: torch.Tensor, map_out=None,
+              raise_on_not_converged: bool = True):
+    """Returns the agc_solve_info.  With raise_on_not_converged False, a solve
+    stopped at max_iter / max_refine returns its info (x then holds P times the
+    last coarse iterate) instead of raising NotConverged."""
     info = agc_solve_info()
-    _check(ctx.h, _lib.agc_solve(ctx.h, byref(prob), byref(opts), _ptr(x), _ptr(map_out), byref(info)))
+    st = _lib.agc_solve(ctx.h, byref(prob), byref(opts), _ptr(x), _ptr(map_out), byref(info))
+    if st == AGC_ERR_NOT_CONVERGED and not raise_on_not_converged:
+        return info
+    _check(ctx.h, st)
     return info
 
 

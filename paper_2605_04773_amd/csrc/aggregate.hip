@@ -175,11 +175,14 @@ static unsigned gs_blocks(int64_t n) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
-int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags, int32_t* map) {
+__global__ void k_clear_u32(unsigned* __restrict__ w) { *w = 0u; }
+
+int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags, int32_t* map,
+                       const AggScratch& s) {
   if (n == 0) return 0;
-  int32_t* parent = c->ws.get<int32_t>("agg.parent", n);
-  uint32_t* flag = c->ws.get<uint32_t>("agg.flag", n + 1);
-  err_reset(c);
+  int32_t* parent = s.parent;
+  uint32_t* flag = s.flag;
+  k_clear_u32<<<1, 1, 0, c->stream>>>(c->d_err);
   k_cc_init<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
   AGC_LAUNCH_CHECK();
   if (m > 0) {
@@ -194,13 +197,29 @@ int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, co
   }
   k_cc_compress<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n, flag);
   AGC_LAUNCH_CHECK();
-  scan_u32(c, flag, flag, n, "agg.scan");
+  scan_u32_into(c, flag, flag, n, s.scan_sums);
   k_cc_label<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, flag, n, map);
   AGC_LAUNCH_CHECK();
-  uint32_t nc = 0;
-  AGC_HIP(hipMemcpyAsync(&nc, flag + n, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-  err_throw(err_fetch(c));
-  return (int32_t)nc;
+  uint32_t* h = (uint32_t*)c->h_pcg;   // pinned scratch of the context; no PCG is in flight here
+  AGC_HIP(hipMemcpyAsync(h, flag + n, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  err_throw(err_fetch(c));   // synchronises
+  return (int32_t)h[0];
+}
+
+int64_t agg_scratch_words(int32_t n) { return 2 * ((int64_t)n + 64) + scan_sums_words(n) + 64; }
+
+AggScratch agg_scratch_carve(uint32_t* base, int32_t n) {
+  AggScratch s;
+  s.parent = reinterpret_cast<int32_t*>(base);
+  s.flag = base + ((int64_t)n + 64);
+  s.scan_sums = base + 2 * ((int64_t)n + 64);
+  return s;
+}
+
+int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags, int32_t* map) {
+  if (n == 0) return 0;
+  uint32_t* base = c->ws.get<uint32_t>("agg.scratch", agg_scratch_words(n));
+  return aggregate_into(c, n, m, edges, tags, map, agg_scratch_carve(base, n));
 }
 
 // ------------------------------------------------------------- members
@@ -212,6 +231,18 @@ __global__ void k_members_init(const int32_t* __restrict__ map, int32_t n, int32
     if (c < 0 || c >= n_c) atomicOr(err, kErrMap);
     k[i] = (uint32_t)(c < 0 ? 0 : (c >= n_c ? n_c - 1 : c));
     v[i] = (uint32_t)i;
+  }
+}
+
+// Over the sorted labels: every label in [0, n_c) must occur (the first is 0,
+// the last n_c - 1, and neighbours differ by at most one), or the segment
+// index of a label would not be the label itself.
+__global__ void k_members_check(const uint32_t* __restrict__ k, int32_t n, int32_t n_c, unsigned* err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = k[i];
+    bool bad = (i == 0) ? c != 0u : c - k[i - 1] > 1u;
+    if (i == n - 1) bad = bad || c != (uint32_t)(n_c - 1);
+    if (bad) atomicOr(err, kErrUnused);
   }
 }
 
@@ -228,6 +259,8 @@ void group_members(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, u
     AGC_HIP(hipMemcpyAsync(mkeys, k2, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
     AGC_HIP(hipMemcpyAsync(members, v2, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c->stream));
   }
+  k_members_check<<<gs_blocks(n), kWG, 0, c->stream>>>(mkeys, n, n_c, c->d_err);
+  AGC_LAUNCH_CHECK();
 }
 
 struct RestrictOp {
@@ -249,8 +282,9 @@ struct RestrictOp {
   }
 };
 
-// members/mkeys from group_members; every coarse id has at least one member,
-// so segment s is coarse node s.
+// members/mkeys from group_members, which flags a label without members
+// (the caller fetches the error word); with every label used, segment s is
+// coarse node s.
 void restrict_sorted(agc_context* c, int32_t n, int32_t n_c, const uint32_t* members, const uint32_t* mkeys,
                      const double* v, double* v_c) {
   (void)n_c;

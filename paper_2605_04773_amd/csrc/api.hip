@@ -105,6 +105,7 @@ struct SolveResult {
   int32_t iters = 0, refine = 0;
   double rel = 0.0;
   int64_t nnzb = 0;
+  bool converged = true;   // false: max_iter (or max_refine) ended the solve; x_c is its last iterate
 };
 
 // rhs_fine: the fine vector whose restriction is the right-hand side (g, or w for the adjoint);
@@ -134,7 +135,9 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   if (!mixed) {
     int32_t it = 0;
     double rel = 0.0;
-    check_status(agc::pcg(c, A64, b_c, x_c, o->rtol, o->max_iter, &it, &rel, true), "coarse PCG");
+    const int st = agc::pcg(c, A64, b_c, x_c, o->rtol, o->max_iter, &it, &rel, true);
+    if (st == AGC_ERR_NOT_CONVERGED) res.converged = false;
+    else check_status(st, "coarse PCG");
     res.iters = it;
     // float64 residual of the returned iterate
     agc::spmv(c, A64, x_c, y);
@@ -149,8 +152,10 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   int32_t used = 0;
   for (int k = 0;; ++k) {
     if (rel <= o->rtol) break;
-    if (k >= o->max_refine || used >= o->max_iter)
-      throw Error(AGC_ERR_NOT_CONVERGED, "mixed refinement did not reach rtol");
+    if (k >= o->max_refine || used >= o->max_iter) {   // x_c keeps the last refined iterate
+      res.converged = false;
+      break;
+    }
     int32_t it = 0;
     double irel = 0.0;
     // the inner tolerance is relative to ||r_c||; never ask for more than rtol needs
@@ -593,6 +598,9 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
     info->fine_rel_res0 = fine_rel0;
     info->ms_post = tm.ms(4, 5);
   }
+  if (!res.converged)
+    throw Error(AGC_ERR_NOT_CONVERGED, "coarse PCG did not reach rtol within max_iter / max_refine: x holds P times "
+                                       "the last coarse iterate");
   API_END(c)
 }
 
@@ -637,6 +645,9 @@ agc_status agc_solve_backward(agc_context* c, const agc_problem* p, const agc_so
     info->refine_iters = res.refine;
     info->rel_res = res.rel;
   }
+  if (!res.converged)
+    throw Error(AGC_ERR_NOT_CONVERGED, "adjoint PCG did not reach rtol within max_iter / max_refine: dg and dH are "
+                                       "those of the last coarse iterate");
   API_END(c)
 }
 

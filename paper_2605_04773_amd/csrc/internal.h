@@ -114,7 +114,25 @@ void err_reset(agc_context* c);
 unsigned err_fetch(agc_context* c);   // synchronises
 void err_throw(unsigned bits);        // throws on a nonzero word
 
+// out[0..n] = exclusive scan as scan_u32, with the caller's buffer of
+// scan_sums_words(n) words for the tile sums (no workspace)
+int64_t scan_sums_words(int64_t n);
+void scan_u32_into(agc_context* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* sums);
+
 // ------------------------------------------------------------ aggregation
+// Scratch of one aggregation of n vertices, carved from agg_scratch_words(n)
+// 32-bit words by agg_scratch_carve (256-byte aligned base).
+struct AggScratch {
+  int32_t* parent = nullptr;     // [n]
+  uint32_t* flag = nullptr;      // [n + 1]
+  uint32_t* scan_sums = nullptr; // [scan_sums_words(n)]
+};
+int64_t agg_scratch_words(int32_t n);
+AggScratch agg_scratch_carve(uint32_t* base, int32_t n);
+// map and n_coarse with the given scratch; allocates nothing (synchronises)
+int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags,
+                       int32_t* map, const AggScratch& s);
+// the same with scratch from the context's workspace
 int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags,
                   int32_t* map);
 // members[k]: vertices sorted by (map, id); mkeys[k] = map[members[k]]

@@ -92,13 +92,25 @@ __global__ __launch_bounds__(kWG) void k_scan_apply(const uint32_t* __restrict__
   if (offs && w == tiles - 1 && threadIdx.x == 0) out[n] = offs[tiles];
 }
 
+int64_t scan_sums_words(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
 void scan_u32(agc_context* c, const uint32_t* in, uint32_t* out, int64_t n, const std::string& tag) {
   if (n <= 0) {
     AGC_HIP(hipMemsetAsync(out, 0, sizeof(uint32_t), c->stream));
     return;
   }
+  scan_u32_into(c, in, out, n, c->ws.get<uint32_t>(tag + ".sums", scan_sums_words(n)));
+}
+
+__global__ void k_zero_first(uint32_t* __restrict__ out) { *out = 0u; }
+
+void scan_u32_into(agc_context* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* sums) {
+  if (n <= 0) {
+    k_zero_first<<<1, 1, 0, c->stream>>>(out);
+    AGC_LAUNCH_CHECK();
+    return;
+  }
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;
-  uint32_t* sums = c->ws.get<uint32_t>(tag + ".sums", tiles + 1);
   k_scan_sums<<<(unsigned)tiles, kWG, 0, c->stream>>>(in, n, sums);
   AGC_LAUNCH_CHECK();
   if (tiles <= kScanDirectTiles) {
@@ -239,6 +251,7 @@ void err_throw(unsigned bits) {
   if (bits & kErrTag) m += " tag not 0 or 1;";
   if (bits & kErrElem) m += " element with a repeated or out-of-range vertex;";
   if (bits & kErrMap) m += " map value out of range;";
+  if (bits & kErrUnused) m += " a coarse label in [0, n_coarse) has no member;";
   if (bits & kErrNoDiag) m += " row without a diagonal block;";
   if (bits & kErrDegenerate) m += " rest element with zero volume;";
   int code = AGC_ERR_BAD_INPUT;

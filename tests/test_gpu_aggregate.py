@@ -144,3 +144,27 @@ def test_restrict_deterministic(ctx):
     a = agc.agc_restrict(ctx, mp, nref, v)
     b = agc.agc_restrict(ctx, mp, nref, v)
     assert torch.equal(a, b)
+
+
+def test_restrict_rejects_unused_label(ctx):
+    """A map that leaves a label in [0, n_coarse) without members is rejected
+    (BAD_INPUT), by agc_restrict and by agc_assemble_coarse's g_c, rather than
+    shifting the sums of every later label; a map that uses every label passes."""
+    import torch
+    agc = binding()
+    p = problem("c1")
+    ref, nref = oagg.components(p["n_verts"], p["edges"], p["tags"])
+    v = torch.from_numpy(p["g"]).to(ctx.device)
+    gap = ref.astype(np.int64)
+    gap[gap >= 5] += 1                       # label 5 unused, n_coarse one larger
+    mp = torch.from_numpy(gap.astype(np.int32)).to(ctx.device)
+    with pytest.raises(agc.BadInput):
+        agc.agc_restrict(ctx, mp, nref + 1, v)
+    short = ref.astype(np.int32)              # n_coarse one too large: the last label unused
+    with pytest.raises(agc.BadInput):
+        agc.agc_restrict(ctx, torch.from_numpy(short).to(ctx.device), nref + 1, v)
+    d = Dev(ctx, p)
+    with pytest.raises(agc.AgcError):
+        agc.agc_assemble_coarse(ctx, d.mesh, d.eh, d.g, mp, nref + 1)
+    out = agc.agc_restrict(ctx, torch.from_numpy(ref).to(ctx.device), nref, v)
+    assert np.allclose(out.cpu().numpy(), ogal.restrict(ref, nref, p["g"]), rtol=1e-12, atol=1e-12)

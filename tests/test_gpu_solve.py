@@ -349,3 +349,45 @@ def test_pcg_hub_rows(ctx, dtype):
     rel = osol.relative_residual(h["a_c"], h["b_c"], xc)
     log(f"   iters={info.iters} rel_res={info.rel_res:.2e} oracle_rel={rel:.2e}")
     assert rel <= (1e-8 if dtype == "f64" else 1e-4)
+
+
+def test_not_converged_prolongates_last_iterate(ctx):
+    """A coarsened solve stopped by max_iter returns NOT_CONVERGED with
+    x = P x_c for its last coarse iterate x_c: here one PCG iteration, which
+    agc_pcg reproduces on the same coarse system from x0 = 0.  The mixed path
+    stopped by max_refine also leaves x constant on every aggregate, with the
+    float64 residual it reports being the oracle's."""
+    import torch
+    agc = binding()
+    d = dev(ctx, "c1")
+    m, nc, a_c, b_c, _ = oracle_solution("c1")
+    prob = d.problem()
+    n = d.p["n_verts"]
+    x = torch.full((n, 3), float("nan"), dtype=torch.float64, device=ctx.device)
+    mp = torch.empty(n, dtype=torch.int32, device=ctx.device)
+    opts = agc.make_opts(rtol=1e-12, max_iter=1)
+    with pytest.raises(agc.NotConverged):
+        agc.agc_solve(ctx, prob, opts, x, mp)
+    x.fill_(float("nan"))
+    info = agc.agc_solve(ctx, prob, opts, x, mp, raise_on_not_converged=False)
+    assert info.pcg_iters == 1 and np.array_equal(mp.cpu().numpy(), m)
+    A, g_c = agc.agc_assemble_coarse(ctx, d.mesh, d.eh, d.g, mp, nc)
+    x_c = torch.zeros_like(g_c)
+    pinfo = agc.agc_pcg(ctx, A, g_c, x_c, 1e-12, 1, raise_on_not_converged=False)
+    assert pinfo.iters == 1
+    ref = agc.agc_prolongate(ctx, mp, nc, x_c)
+    xs, rs = x.cpu().numpy(), ref.cpu().numpy()
+    assert np.isfinite(xs).all()
+    assert np.allclose(xs, rs, rtol=1e-13, atol=1e-13 * np.abs(rs).max())
+    rel = osol.relative_residual(a_c, b_c, xs[oagg.representatives(m, nc)])
+    assert abs(rel - info.rel_res) <= 1e-9 * rel
+    # mixed, stopped by max_refine after one loose inner solve
+    x.fill_(float("nan"))
+    info = agc.agc_solve(ctx, prob, agc.make_opts(precision=agc.AGC_PREC_MIXED, rtol=1e-12, max_refine=1,
+                                                  inner_rtol=0.5), x, mp, raise_on_not_converged=False)
+    xs = x.cpu().numpy()
+    assert np.isfinite(xs).all() and np.abs(xs).max() > 0
+    rep = oagg.representatives(m, nc)
+    assert np.array_equal(xs, xs[rep][m])
+    rel = osol.relative_residual(a_c, b_c, xs[rep])
+    assert info.refine_iters == 0 and rel < 0.6 and abs(rel - info.rel_res) <= 1e-9 * rel
