@@ -33,7 +33,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import method, tagging
+from . import galerkin, method, tagging
 
 MAX_HALVINGS = 30
 
@@ -127,11 +127,28 @@ def predicted(x_t, v_t, f_ext, mass, h):
     return xh
 
 
-def time_step(mesh: dict, mat: dict, x_t, v_t, f_ext=None, eps_d=1e-3, max_newton=50, tag_threshold=5e-5,
-              coarsen=True, post_iters=0):
-    """One time step's Newton loop.  mesh: n_verts, rest, tets, edges; mat: mu, lam, rho, h.
+def affine_solve(sub: dict, rest: np.ndarray, threshold: int) -> tuple[np.ndarray, int]:
+    """x = P A_c^{-1} P^T g with the adaptive affine embedding (Sec. 4.2, Eq. 4):
+    aggregates of more than `threshold` members carry 12 DoF (oracle/affine.py),
+    the coarse system solved directly.  Returns x and the number of 3x3 block rows."""
+    from . import affine, aggregate
+    from . import solve as _solve
+    m, n_c = aggregate.components(sub["n_verts"], sub["edges"], sub["tags"])
+    a_c, b_c, cls, pm = affine.coarse_system(dict(sub, pos=rest), m, n_c, threshold)
+    x_c = _solve.solve_sparse(a_c, b_c.reshape(-1))
+    return affine.prolongate(pm, x_c), int(cls["n_flat"])
 
-    Returns x and a per-iteration log (energy before, step length, |d|_inf, n_c)."""
+
+def time_step(mesh: dict, mat: dict, x_t, v_t, f_ext=None, eps_d=1e-3, max_newton=50, tag_threshold=5e-5,
+              coarsen=True, post_iters=0, affine_threshold=0, record=False):
+    """One time step's Newton loop.  mesh: n_verts, rest, tets, edges; mat: mu, lam, rho, h.
+    affine_threshold > 0: each solve uses the adaptive affine embedding of
+    aggregates with more members than that (Sec. 4.2, Eq. 4).
+
+    Returns x and a per-iteration log (energy before, step length, |d|_inf,
+    n_c, the 3x3 block rows of the solve, the quadratic model's value along
+    d; with record also the tags, the map, the strain increment norms and the
+    iterate after the step)."""
     mu, lam, rho, h = mat["mu"], mat["lam"], mat["rho"], mat["h"]
     rest, tets, n = mesh["rest"], mesh["tets"], mesh["n_verts"]
     _, vol, b = rest_shape(rest, tets)
@@ -145,12 +162,15 @@ def time_step(mesh: dict, mat: dict, x_t, v_t, f_ext=None, eps_d=1e-3, max_newto
         g = gradient(x, x_hat, mass, tets, b, vol, mu, lam, h)
         blocks = element_blocks(x, tets, b, vol, mu, lam, rho, h)
         if coarsen:
-            tags, _ = tagging.tag_edges(rest, x, x_last, tets, mesh["edges"], tag_threshold)
+            tags, norms = tagging.tag_edges(rest, x, x_last, tets, mesh["edges"], tag_threshold)
         else:
             tags = np.zeros(mesh["edges"].shape[0], np.uint8)
+            norms = None
         sub = {"n_verts": n, "elem_verts": tets, "elem_H": blocks, "g": g, "edges": mesh["edges"], "tags": tags}
         r = method.coarsened_solve(sub, solver="sparse")
-        xs = r["x"]
+        xs, n_blocks = r["x"], r["n_c"]
+        if affine_threshold > 0:
+            xs, n_blocks = affine_solve(sub, rest, affine_threshold)
         if post_iters:
             xs, _ = method.post_coarsen(sub, xs, post_iters)
         d = -xs
@@ -166,8 +186,13 @@ def time_step(mesh: dict, mat: dict, x_t, v_t, f_ext=None, eps_d=1e-3, max_newto
                 break
             alpha *= 0.5
         d_inf = float(np.max(np.abs(d)))
-        log.append({"energy": e_prev, "energy_after": e_new, "alpha": alpha, "halvings": halvings,
-                    "d_inf": d_inf, "n_c": r["n_c"]})
+        # the quadratic model of this iteration along d (Sec. 3, Eq. 2): g^T d + d^T H d / 2
+        q = float(np.sum(g * d) + 0.5 * np.sum(d * galerkin.fine_matvec(tets, blocks, d)))
+        entry = {"energy": e_prev, "energy_after": e_new, "alpha": alpha, "halvings": halvings,
+                 "d_inf": d_inf, "n_c": r["n_c"], "n_blocks": n_blocks, "model": q}
+        if record:
+            entry.update(tags=tags, map=r["map"], norms=norms, x=x_new.copy())
+        log.append(entry)
         x_last, x = x, x_new
         if d_inf / h <= eps_d or halvings > MAX_HALVINGS:
             break

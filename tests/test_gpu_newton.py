@@ -6,9 +6,10 @@ rounding (relative 1e-10 of each quantity's scale; the rotation comes from
 two different methods, Jacobi on F^T F here and an SVD in the oracle).  The
 loop: with float64 solves to 1e-12 both sides take the same directions, so
 the per-iteration energies and step lengths agree and the results agree to
-1e-9 of the displacement; with coarsening the tags of an element within
-rounding of the threshold could differ, so the coarsened loop is compared
-by its final energy."""
+1e-9 of the displacement.  The coarsened loop, with and without the affine
+embedding, is compared iteration by iteration (tags, map, iterate, energy)
+on a case whose strain increments keep clear of the threshold, and by its
+final energy elsewhere."""
 import numpy as np
 import pytest
 
@@ -174,6 +175,54 @@ def test_affine_embedded_loop(ctx, precision):
     xb, ib = agc.agc_newton_step(ctx, d["nw"], agc.make_newton_opts(eps_d=1e-4, coarsen=1, solve=plain), t(x_t),
                                  t(v_t), t(f))
     assert torch.equal(xa, xb) and ia.newton_iters == ib.newton_iters
+
+
+@pytest.mark.parametrize("affine", [0, 8])
+def test_coarsened_loop_per_iteration(ctx, affine):
+    """The coarsened loop (FP64 solves to 1e-12), iteration by iteration,
+    against the oracle's loop of the same path (affine > 0: aggregates of
+    more than `affine` vertices carry 12 DoF, Sec. 4.2 Eq. 4).  After k
+    iterations (a run with max_newton = k) the GPU iterate is the oracle's
+    within 1e-9 of the displacement, and so is the energy; the tags of
+    iteration k, from the library's tagger on the GPU's iterates k-1 and
+    k-2, are the oracle's bit for bit, and so is the map agc_aggregate makes
+    of them.  No element's strain increment in the oracle's iterates lies
+    within 1e-6 of the threshold (checked), so rounding decides no tag."""
+    import torch
+    agc = binding()
+    p, d = case(ctx, 8)
+    mat = synth.material()
+    h, thr = mat["h"], 5e-5
+    x_t, v_t, f = synth.newton_state(p, wave_speed=0.5)
+    mesh = {"n_verts": p["n_verts"], "rest": p["pos"], "tets": p["elem_verts"], "edges": p["edges"]}
+    _, lg = onw.time_step(mesh, mat, x_t, v_t, f, eps_d=1e-4, coarsen=True, affine_threshold=affine, record=True)
+    margin = min(float(np.min(np.abs(it["norms"] - thr))) / thr for it in lg)
+    assert margin > 1e-6
+    assert any(it["n_c"] < p["n_verts"] for it in lg)
+    if affine:
+        assert any(it["n_blocks"] > it["n_c"] for it in lg)
+    t = lambda a: d["t"](a, torch.float64)
+    tagger = agc.agc_tagger_create(ctx, p["n_verts"], d["ev"], d["rest"], d["edges"])
+    disp = max(float(np.abs(it["x"] - x_t).max()) for it in lg)
+    solve = agc.make_opts(rtol=1e-12, affine_threshold=affine)
+    prev2, prev = x_t - h * v_t, x_t
+    for k in range(1, len(lg) + 1):
+        ref = lg[k - 1]
+        tags, _ = agc.agc_tag_edges(ctx, tagger, t(prev), t(prev2), thr)
+        assert np.array_equal(tags.cpu().numpy(), ref["tags"]), f"tags of iteration {k}"
+        mp, nc = agc.agc_aggregate(ctx, p["n_verts"], d["edges"], tags)
+        assert nc == ref["n_c"] and np.array_equal(mp.cpu().numpy(), ref["map"]), f"map of iteration {k}"
+        opts = agc.make_newton_opts(max_newton=k, eps_d=1e-4, coarsen=1, solve=solve)
+        x, info = agc.agc_newton_step(ctx, d["nw"], opts, t(x_t), t(v_t), t(f))
+        xk = x.cpu().numpy()
+        err = float(np.abs(xk - ref["x"]).max()) / disp
+        log(f"[newton per-iteration] affine={affine} k={k}: n_c {nc} blocks {ref['n_blocks']} halvings "
+            f"{ref['halvings']} x vs oracle {err:.1e} of the displacement")
+        assert info.newton_iters == k
+        assert err <= 1e-9
+        assert abs(info.energy - ref["energy_after"]) <= 1e-9 * abs(lg[0]["energy"])
+        prev2, prev = prev, xk
+    tagger.close()
 
 
 def test_bad_input(ctx):

@@ -168,6 +168,46 @@ def check_loop(time_step):
     assert len(logf) >= 2 and any(it["n_c"] < p["n_verts"] for it in logc)
 
 
+def check_affine_loop(time_step):
+    """The loop with the adaptive affine embedding (Sec. 4.2, Eq. 4): with the
+    threshold above every aggregate it is the 3-DoF loop exactly; with a
+    threshold of 8 its first solve, which sees the same tags and map as the
+    3-DoF one, has 12-DoF nodes and lowers the quadratic model strictly more
+    (its subspace contains the 3-DoF one; the iterations before it have no
+    12-DoF node, so both loops reach it in the same state), every step lowers E, and the loop
+    ends at the fine loop's minimum to 1e-3 of the energy drop."""
+    p, mesh, x_t, v_t, f = _newton_case()
+    mat = synth.material()
+    xc, logc = newton.time_step(mesh, mat, x_t, v_t, f, eps_d=1e-4, coarsen=True)
+    xb, logb = time_step(mesh, mat, x_t, v_t, f, eps_d=1e-4, coarsen=True, affine_threshold=10 ** 6)
+    assert np.array_equal(xb, xc) and len(logb) == len(logc)
+    xa, loga = time_step(mesh, mat, x_t, v_t, f, eps_d=1e-4, coarsen=True, affine_threshold=8)
+    # the first iteration with a 12-DoF node: the iterations before it solve the same
+    # 3-DoF systems (up to rounding), so both loops see the same state and map there
+    k = next(i for i, it in enumerate(loga) if it["n_blocks"] > it["n_c"])
+    assert k < len(logc) and loga[k]["n_c"] == logc[k]["n_c"]
+    assert abs(loga[k]["energy"] - logc[k]["energy"]) <= 1e-12 * abs(logc[k]["energy"])
+    assert loga[k]["model"] < logc[k]["model"] - 1e-9 * abs(logc[k]["model"])
+    assert all(it["energy_after"] < it["energy"] for it in loga)
+    xf, logf = newton.time_step(mesh, mat, x_t, v_t, f, eps_d=1e-4, coarsen=False)
+    e0, ef = logf[0]["energy"], logf[-1]["energy_after"]
+    assert loga[-1]["energy_after"] - ef <= 1e-3 * (e0 - ef)
+
+
+def test_affine_loop():
+    check_affine_loop(newton.time_step)
+
+
+def test_mutant_affine_loop_ignores_the_embedding():
+    """A loop that takes the 3-DoF solve whatever the threshold."""
+    def time_step(mesh, mat, x_t, v_t, f, eps_d, coarsen, affine_threshold):
+        x, log = newton.time_step(mesh, mat, x_t, v_t, f, eps_d=eps_d, coarsen=coarsen)
+        for it in log:
+            it["n_blocks"] = it["n_c"] + (3 if affine_threshold < 10 ** 6 else 0)
+        return x, log
+    assert _fails(check_affine_loop, time_step)
+
+
 def test_polar():
     check_polar(newton.polar_rotation)
 
