@@ -72,42 +72,54 @@ def test_gradient_mixed_precision(ctx):
 
 
 def test_central_differences(ctx):
-    """FD of the GPU forward along random directions of g and of symmetric element perturbations."""
+    """Central differences of the GPU forward at the 32^3 grid (eps = 1e-6,
+    relative): 16 random directions of g (||d|| = ||g||) and 16 random
+    symmetric element perturbations (||D_e||_F = ||H_e||_F per element).
+    Every +/- solve runs the same fixed number of PCG iterations (the count
+    that reaches rtol 1e-13 on the unperturbed system; the library is asked
+    for an unreachable 1e-16 and stops at max_iter), so the differences are
+    not polluted by differing stop points."""
     import torch
     agc = binding()
-    p = problem("c1")
+    p = problem("c4")
     d = Dev(ctx, p)
     rng = np.random.default_rng(4)
     w = torch.from_numpy(synth.adjoint_seed(p)).to(ctx.device)
-    opts = agc.make_opts(rtol=1e-14, max_iter=20000)
-    x, L, dg, dh = _forward_backward(ctx, d, w, opts)
+    x, L, dg, dh = _forward_backward(ctx, d, w, agc.make_opts(rtol=1e-13, max_iter=20000))
+    probe = agc.agc_solve(ctx, d.problem(), agc.make_opts(rtol=1e-13, max_iter=20000), torch.empty_like(d.g))
+    fixed = agc.make_opts(rtol=1e-16, max_iter=probe.pcg_iters)
+    log(f"[fd] 32^3: {probe.pcg_iters} PCG iterations per solve, L = {L:.6e}")
 
     def loss(g, eh):
         xx = torch.empty_like(g)
         prob = agc.make_problem(d.mesh, d.edges, d.tags, eh, g)
-        try:
-            agc.agc_solve(ctx, prob, opts, xx)
-        except agc.NotConverged:
-            pass
+        info = agc.agc_solve(ctx, prob, fixed, xx, raise_on_not_converged=False)
+        assert info.pcg_iters == probe.pcg_iters
         return float((xx * w).sum())
 
     eps = 1e-6
-    for _ in range(4):
+    worst = 0.0
+    for _ in range(16):
         dd = rng.standard_normal(p["g"].shape)
         dd *= np.linalg.norm(p["g"]) / np.linalg.norm(dd)
         dt = torch.from_numpy(dd).to(ctx.device)
         fd = (loss(d.g + eps * dt, d.eh) - loss(d.g - eps * dt, d.eh)) / (2 * eps)
         an = float((dg * dt).sum())
-        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-7 * abs(L)
+        worst = max(worst, abs(fd - an) / (abs(an) + 1e-300))
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-8 * abs(L)
     he = p["elem_H"].reshape(-1, 12, 12)
-    for _ in range(4):
+    hn = np.linalg.norm(he, axis=(1, 2))
+    for _ in range(16):
         dd = rng.standard_normal(he.shape)
         dd = 0.5 * (dd + np.swapaxes(dd, 1, 2))
-        dd *= (np.linalg.norm(he, axis=(1, 2)) / np.linalg.norm(dd, axis=(1, 2)))[:, None, None]
+        dd *= (hn / np.linalg.norm(dd, axis=(1, 2)))[:, None, None]
         dt = torch.from_numpy(dd.reshape(-1, 144)).to(ctx.device)
+        del dd
         fd = (loss(d.g, d.eh + eps * dt) - loss(d.g, d.eh - eps * dt)) / (2 * eps)
         an = float((dh * dt).sum())
-        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-7 * abs(L)
+        worst = max(worst, abs(fd - an) / (abs(an) + 1e-300))
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-8 * abs(L)
+    log(f"   worst relative FD mismatch over 32 directions: {worst:.2e}")
 
 
 def test_backward_keeps_only_the_map(ctx):
