@@ -1,25 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark: ms per Newton linear solve (coarsen + assemble + PCG + prolong) vs fine PCG, on one GPU.
 
-Workload (default ``c2``): unit cube as a 64^3 grid of cubes, 5 tets per cube
-(274,625 vertices, 1,310,720 tets), co-rotated linear elasticity E=1e5 Pa,
-nu=0.4, rho=1000, lumped mass / h^2 with h=1e-2, 60% of edges collapsible
-(sublevel set of a smooth random field), g ~ N(0,1).  Synthetic, seeded.
+Default workload (``--config c5``): the unit cube as a 128^3 grid of cubes, 5
+tets per cube (2,146,689 vertices, 10,485,760 tets), co-rotated linear
+elasticity E=1e5 Pa, nu=0.4, rho=1000, lumped mass / h^2 with h=1e-2, g ~
+N(0,1), and ten successive systems whose edge tags (60% collapsible, the
+sublevel set of a smooth random field) drift by about 10% from one system to
+the next, so that every solve re-aggregates and re-assembles.  Synthetic,
+seeded; every input is resident in GPU memory before the timed region.
 
-One step = one agc_solve: aggregation, coarse assembly from the element
-blocks, PCG, prolongation.  The measured path is the mixed-precision
-coarsened solve (float32 storage and SpMV values in the inner PCG; float64
-assembly sums, vectors, inner products, residuals and iterative refinement)
-to a float64 relative residual of --rtol.  Beside it, the same number of steps of the plain FP64
-fine solve (fine assembly + fine block-Jacobi PCG, same tolerance) and of the
-FP64 coarsened solve are timed on the same GPU.
+One step = one agc_solve in FP64 (the paper's precision): aggregation,
+coarse assembly from the element blocks, block-Jacobi PCG to a float64
+relative residual of --rtol, prolongation.  The K timed steps are spread
+evenly over the ten systems (K // 10 or K // 10 + 1 each, after every
+system's untimed float64 reference solve and W untimed warm-up solves);
+``value`` is the median over the systems of their mean ms per solve.  Beside
+it, measured the same way: the mixed-precision coarsened solve (float32
+matrix values in the inner PCG, float64 sums, vectors, inner products,
+residuals and iterative refinement) and the plain FP64 fine solve (fine
+assembly + fine block-Jacobi PCG, --rtol-fine) on the same GPU.  Errors are
+against each system's float64 solve to rtol 1e-12 (the GPU parity tests
+certify those with the oracle).  Unless --no-extras, the 64^3 grid's
+figures (FP64, mixed and fine solves, post-coarsening, affine embedding,
+edge tagging, the adjoint and one Newton time step) follow under "c2".
+
+``--config c1 .. c4`` measures that single system instead (value: the FP64
+coarsened solve).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -31,28 +46,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "ms per Newton linear solve (coarsen+assemble+PCG+prolong) vs fine PCG, 1 GPU"
+N_DRIFT_SYSTEMS = 10
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(nnzb, n, value_bytes):
-    """Algorithmic bytes of one fused PCG SpMV launch (w = A z, z^T w).
+def spmv_bytes(nnzb, n, value_bytes, z_bytes):
+    """Algorithmic bytes of one fused PCG SpMV launch (w = A z and z^T w).
 
-    Per stored 3x3 block: 9 values, its column index and its row index.
-    Per block row: z read once, w written once.
-    """
-    return nnzb * (9 * value_bytes + 4 + 4) + n * (24 + 24)
+    Per stored 3x3 block: its 9 values and its column index.  Per block row:
+    the row pointer, z read once (3 values of z_bytes), w written once (3
+    float64).  The row index the kernel also reads per block (its layout's
+    choice, for nonzero balancing) is not algorithmic: it shows in the
+    counter traffic instead."""
+    return nnzb * (9 * value_bytes + 4) + n * (4 + 3 * z_bytes + 24)
 
 
-STEP_MS = {}
+def assembly_bytes(n_elems, n_verts, nnzb_coarse, value_bytes=8):
+    """Algorithmic bytes of one coarse assembly: every element's ids and 144
+    values read once, g and the map per vertex, the coarse BSR written once."""
+    return n_elems * (16 + 144 * value_bytes) + n_verts * (24 + 4) + nnzb_coarse * (9 * value_bytes + 4)
 
 
-def time_steps(fn, steps, warmup, torch, key=None):
-    """Mean ms per call over `steps` calls after `warmup`, bracketed by device
-    synchronisations.  With `key`, the per-call times (each call returns host
-    scalars, so it has synchronised its stream) are kept in STEP_MS[key]."""
+def spread(ms):
+    q = np.percentile(ms, [10, 50, 90])
+    return {"p10": round(float(q[0]), 4), "median": round(float(q[1]), 4), "p90": round(float(q[2]), 4),
+            "n": int(len(ms))}
+
+
+def time_steps(fn, steps, warmup, torch):
+    """Per-call ms of `steps` calls after `warmup`, and the last result.  Each
+    call returns host scalars (it has synchronised its stream); the region is
+    bracketed by device synchronisations."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -62,24 +90,19 @@ def time_steps(fn, steps, warmup, torch, key=None):
         last = fn()
         marks.append(time.perf_counter())
     torch.cuda.synchronize()
-    if key is not None:
-        STEP_MS[key] = np.diff(np.array([t0] + marks)) * 1e3
-    return (time.perf_counter() - t0) * 1e3 / steps, last
+    return np.diff(np.array([t0] + marks)) * 1e3, last
 
 
-def spread(ms):
-    q = np.percentile(ms, [10, 50, 90])
-    return {"p10": round(float(q[0]), 4), "median": round(float(q[1]), 4), "p90": round(float(q[2]), 4),
-            "n": int(len(ms))}
+# ------------------------------------------------------------ HBM counters
 
-
-PAPER_ROW_BODIES = 96
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pcg_spmv_float_c2_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_04773_amd", "csrc", f) for f in ("pcg.hip", "common.h")]
+TRAFFIC_FILES = {
+    ("c5", "f64"): os.path.join(ROOT, "profiles", "k_pcg_spmv_double_c5_hbm_traffic.md"),
+    ("c2", "f32"): os.path.join(ROOT, "profiles", "k_pcg_spmv_float_c2_hbm_traffic.md"),
+}
 
 
 def kernel_source_hash() -> str:
-    import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, "rb") as fh:
@@ -87,13 +110,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(config):
-    """HBM bytes per launch of the SpMV from the committed counter summary, or None
-    when there is none for this workload or the kernel source changed since."""
-    if config != "c2" or not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(config, dtype):
+    """HBM bytes per launch of the PCG SpMV from the committed counter summary,
+    or None when there is none for this workload or the kernel source changed since."""
+    path = TRAFFIC_FILES.get((config, dtype))
+    if path is None or not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
@@ -106,28 +130,257 @@ def measured_traffic(config):
         return None
 
 
-def cpu_baseline(p, rtol):
-    """The FP64 oracle, as it stands, on the whole workload: one coarsened solve, one thread."""
-    from threadpoolctl import threadpool_limits
+def roofline(name, nnzb, n, value_bytes, z_bytes, info, traffic):
+    """Achieved bandwidth of the PCG SpMV: algorithmic bytes per launch over the
+    mean duration of its launches replayed between two HIP events on the
+    context's stream (opts.timing = 2)."""
+    avg_ms = info.ms_spmv / max(info.spmv_launches, 1)
+    alg = spmv_bytes(nnzb, n, value_bytes, z_bytes)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "avg_launch_us": round(avg_ms * 1e3, 3), "launches": int(info.spmv_launches),
+            "algorithmic_bytes_per_launch": int(alg)}
 
-    from oracle import method
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        r = method.coarsened_solve(p, solver="pcg", rtol=rtol)
-        ms = (time.perf_counter() - t0) * 1e3
+
+# ------------------------------------------------------------ CPU baseline
+
+def host_info(threads):
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
     except OSError:
         pass
-    return {"value": round(ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "host": {"cpu": model, "os_cpu_count": os.cpu_count(),
-                     "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"), "blas_threads_used": 1},
+    return {"cpu": model, "os_cpu_count": os.cpu_count(), "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+            "blas_threads_used": threads}
+
+
+def oracle_steps(p, tags, rtol):
+    """The oracle's four steps, each timed (ms): components, P^T H P and P^T g, block-Jacobi PCG, P x_c."""
+    from oracle import aggregate, galerkin, solve
+    t = [time.perf_counter()]
+    m, n_c = aggregate.components(p["n_verts"], p["edges"], tags)
+    t.append(time.perf_counter())
+    a_c, b_c = galerkin.coarse_system(p["n_verts"], p["elem_verts"], p["elem_H"], p["g"], m, n_c)
+    t.append(time.perf_counter())
+    x_c, its, _ = solve.pcg(a_c, b_c, rtol, 100000)
+    t.append(time.perf_counter())
+    galerkin.prolongate(m, x_c)
+    t.append(time.perf_counter())
+    ms = np.diff(np.array(t)) * 1e3
+    return {"aggregate": ms[0], "assemble": ms[1], "pcg": ms[2], "prolong": ms[3]}, its, n_c, a_c.nnz // 9
+
+
+def cpu_baseline_single(p, rtol):
+    """The oracle, as it stands, on the whole single-system workload, one thread."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        ms, its, _, _ = oracle_steps(p, p["tags"], rtol)
+    return {"value": round(float(sum(ms.values())), 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "host": host_info(1), "step_ms": {k: round(float(v), 1) for k, v in ms.items()},
             "sample": f"the whole workload: one coarsened solve (canonical components, sparse P^T H P, "
-                      f"block-Jacobi PCG to rtol {rtol:g} in {r['iters']} iterations, prolongation), "
+                      f"block-Jacobi PCG to rtol {rtol:g} in {its} iterations, prolongation), "
                       f"numpy/scipy single-threaded"}
 
+
+def slab(p, tags, layers):
+    """The sub-problem of the cubes in the lowest `layers` layers of a grid: its
+    vertices are a prefix of the ids, its tets the first ones of the list."""
+    n1 = round(p["n_verts"] ** (1.0 / 3.0))
+    nv = n1 * n1 * (layers + 1)
+    ne = 5 * (n1 - 1) * (n1 - 1) * layers
+    ev = p["elem_verts"][:ne]
+    assert int(ev.max()) < nv
+    keep = (p["edges"][:, 0] < nv) & (p["edges"][:, 1] < nv)
+    return {"n_verts": nv, "elem_verts": ev, "elem_H": p["elem_H"][:ne], "g": p["g"][:nv],
+            "edges": p["edges"][keep]}, tags[keep]
+
+
+def cpu_baseline_slab(p, tags, rtol, layers, full):
+    """The oracle, as it stands, on a bounded sample of system 0: the slab of
+    the lowest `layers` cube layers of the grid (same tags, mesh, element
+    blocks and g).  Each oracle step is timed; the steps whose work grows with
+    the mesh are scaled by the element ratio, the PCG by the ratio of its
+    per-iteration work (stored blocks) and of the iteration counts (the GPU's
+    on the full system over the oracle's on the slab)."""
+    from threadpoolctl import threadpool_limits
+    q, qt = slab(p, tags, layers)
+    with threadpool_limits(1):
+        ms, its, n_c, nnzb = oracle_steps(q, qt, rtol)
+    ratio_e = p["elem_verts"].shape[0] / q["elem_verts"].shape[0]
+    ratio_v = p["n_verts"] / q["n_verts"]
+    ratio_pcg = (full["nnzb"] / max(nnzb, 1)) * (full["iters"] / max(its, 1))
+    scaled = {"aggregate": ms["aggregate"] * ratio_e, "assemble": ms["assemble"] * ratio_e,
+              "pcg": ms["pcg"] * ratio_pcg, "prolong": ms["prolong"] * ratio_v}
+    sample_ms = float(sum(ms.values()))
+    return {"value": round(float(sum(scaled.values())), 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "host": host_info(1),
+            "sample": (f"system 0, slab of the lowest {layers} of {round(p['n_verts'] ** (1 / 3)) - 1} cube layers "
+                       f"({q['n_verts']} vertices, {q['elem_verts'].shape[0]} tets, {q['edges'].shape[0]} edges, "
+                       f"same tags): the oracle's four steps took {sample_ms:.0f} ms (coarse size {n_c}, "
+                       f"{nnzb} blocks, PCG to rtol {rtol:g} in {its} iterations), numpy/scipy single-threaded; "
+                       f"scaled to one full solve: components and assembly x{ratio_e:.2f} (tets), prolongation "
+                       f"x{ratio_v:.2f} (vertices), PCG x{ratio_pcg:.2f} (blocks {full['nnzb']} / {nnzb} times "
+                       f"iterations {full['iters']} / {its})"),
+            "sample_ms": {k: round(float(v), 1) for k, v in ms.items()},
+            "scaled_ms": {k: round(float(v), 1) for k, v in scaled.items()}}
+
+
+# ------------------------------------------------------------ c5: drifting systems
+
+def drift_systems(args, p, ctx, mesh, dev, t, torch, agc, synth, setup_ms):
+    """Ten systems on one mesh whose tags drift by about 10% from one to the next."""
+    from concurrent.futures import ThreadPoolExecutor
+    n_e, n_v = int(p["elem_verts"].shape[0]), int(p["n_verts"])
+    log(f"[bench] drifting tags of {N_DRIFT_SYSTEMS} systems")
+    with ThreadPoolExecutor(max_workers=min(N_DRIFT_SYSTEMS, 8)) as ex:
+        tag_np = list(ex.map(lambda it: synth.drift_tags(p, it), range(N_DRIFT_SYSTEMS)))
+    flips = [None] + [round(float(np.mean(tag_np[i] != tag_np[i - 1])), 4) for i in range(1, N_DRIFT_SYSTEMS)]
+    edges = t(p["edges"], torch.int32)
+    tags = [t(tg, torch.uint8) for tg in tag_np]
+    eh, g = t(p["elem_H"], torch.float64), t(p["g"], torch.float64)
+    rest = t(p["pos"], torch.float64)
+    probs = [agc.make_problem(mesh, edges, tg, eh, g, rest) for tg in tags]
+    x = torch.empty((n_v, 3), dtype=torch.float64, device=dev)
+    mp = torch.empty(n_v, dtype=torch.int32, device=dev)
+
+    def solve(s, **kw):
+        return agc.agc_solve(ctx, probs[s], agc.make_opts(**kw), x, mp)
+
+    def rel(ref):
+        return float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
+
+    # untimed float64 references (rtol 1e-12), one per system
+    refs, ref_info = [], []
+    for s in range(N_DRIFT_SYSTEMS):
+        ref_info.append(solve(s, rtol=1e-12, max_iter=50000))
+        refs.append(x.clone())
+    solve(0, rtol=1e-12, max_iter=50000, coarsen=0)
+    ref_fine = x.clone()
+    torch.cuda.synchronize()
+
+    K, W = args.steps, args.warmup
+    per = [K // N_DRIFT_SYSTEMS + (1 if s < K % N_DRIFT_SYSTEMS else 0) for s in range(N_DRIFT_SYSTEMS)]
+
+    def timed(kw, label):
+        """W warm-up solves (system 0), then K timed solves spread over the systems."""
+        for _ in range(W):
+            solve(0, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = [[] for _ in range(N_DRIFT_SYSTEMS)]
+        infos = [None] * N_DRIFT_SYSTEMS
+        last = t0
+        for s in range(N_DRIFT_SYSTEMS):
+            for _ in range(per[s]):
+                infos[s] = solve(s, **kw)
+                now = time.perf_counter()
+                ms[s].append((now - last) * 1e3)
+                last = now
+        torch.cuda.synchronize()
+        total = (time.perf_counter() - t0) * 1e3
+        means = [float(np.mean(v)) for v in ms if v]
+        med = float(np.median(means))
+        log(f"[bench] {label}: median over systems {med:.3f} ms, mean per step {total / max(K, 1):.3f} ms")
+        return med, total / max(K, 1), ms, infos
+
+    c64_kw = dict(rtol=args.rtol, max_iter=50000)
+    mix_kw = dict(rtol=args.rtol, precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, max_iter=50000)
+    log("[bench] coarsened FP64 solves (the metric)")
+    med64, mean64, ms64, info64 = timed(c64_kw, "coarsened FP64")
+    log("[bench] coarsened mixed-precision solves")
+    medmx, meanmx, msmx, infomx = timed(mix_kw, "coarsened mixed")
+
+    systems = []
+    for s in range(N_DRIFT_SYSTEMS):
+        i64 = solve(s, **c64_kw)
+        e64 = rel(refs[s])
+        ph = solve(s, timing=1, **c64_kw)
+        imx = solve(s, **mix_kw)
+        emx = rel(refs[s])
+        systems.append({
+            "system": s, "flip_fraction": flips[s], "n_coarse": i64.n_coarse, "nnzb_coarse": int(i64.nnzb),
+            "fp64": {"ms": round(float(np.mean(ms64[s])), 3) if ms64[s] else None, "pcg_iters": i64.pcg_iters,
+                     "rel_res": i64.rel_res, "rel_err": e64},
+            "mixed": {"ms": round(float(np.mean(msmx[s])), 3) if msmx[s] else None, "pcg_iters": imx.pcg_iters,
+                      "refine_iters": imx.refine_iters, "rel_err": emx},
+            "fp64_phase_ms": {"aggregate": round(ph.ms_aggregate, 3), "assemble": round(ph.ms_assemble, 3),
+                              "pcg": round(ph.ms_pcg, 3), "prolong": round(ph.ms_prolong, 3)},
+            "assembly_gbs": round(assembly_bytes(n_e, n_v, int(ph.nnzb)) / (ph.ms_assemble * 1e-3) / 1e9, 1),
+        })
+        log(f"[bench] system {s}: flips {flips[s]} n_c={i64.n_coarse} nnzb={i64.nnzb} fp64 iters={i64.pcg_iters} "
+            f"err={e64:.2e}; mixed iters={imx.pcg_iters} err={emx:.2e}; phases agg {ph.ms_aggregate:.2f} "
+            f"asm {ph.ms_assemble:.2f} pcg {ph.ms_pcg:.2f} prl {ph.ms_prolong:.2f} ms")
+
+    # the dominant kernel: the fused SpMV of the FP64 coarse PCG, system 0
+    ti = solve(0, timing=2, **c64_kw)
+    roof = roofline("k_pcg_spmv<double> (fused SpMV w = A z and z^T w, float64 coarse matrix), system 0",
+                    int(ti.nnzb), ti.n_coarse, 8, 8, ti, measured_traffic("c5", "f64"))
+    tm = solve(0, timing=2, **mix_kw)
+    roof_mx = roofline("k_pcg_spmv<float> (float32 coarse matrix, float32 z), system 0", int(tm.nnzb), tm.n_coarse,
+                       4, 4, tm, None)
+    log(f"[bench] SpMV float64 coarse: {roof['avg_launch_us']:.1f} us = {roof['achieved']:.0f} GB/s "
+        f"({roof['frac']:.3f}); float32: {roof_mx['avg_launch_us']:.1f} us ({roof_mx['frac']:.3f})")
+
+    # the fine FP64 comparator (its system does not depend on the tags)
+    log("[bench] fine FP64 solves (comparator)")
+    kf = max(2, K // 2)
+    msf, finfo = time_steps(lambda: solve(0, rtol=args.rtol_fine, coarsen=0, max_iter=50000), kf, 1, torch)
+    err_f = rel(ref_fine)
+    fi = solve(0, rtol=args.rtol_fine, coarsen=0, timing=2, max_iter=50000)
+    roof_f = roofline("k_pcg_spmv<double> on the fine matrix", int(fi.nnzb), fi.n_coarse, 8, 8, fi, None)
+    ms_fine = float(np.mean(msf))
+    log(f"[bench]   {ms_fine:.2f} ms/solve  pcg_iters={finfo.pcg_iters} err={err_f:.2e}; SpMV "
+        f"{roof_f['avg_launch_us']:.1f} us ({roof_f['frac']:.3f})")
+
+    f32in = None
+    if not args.no_extras:
+        f32in = f32_element_input(args, p, ctx, mesh, edges, tags[0], eh, g, refs[0], args.rtol, torch, agc)
+    all64 = [v for s in ms64 for v in s]
+    out = {
+        "metric": METRIC, "value": round(med64, 4), "unit": "ms", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(mean64, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": (f"c5: cube grid 128^3, 5 tets/cube, {n_v} vertices, {n_e} tets, {p['frac']:.0%} collapsible "
+                         f"edges, {N_DRIFT_SYSTEMS} systems whose tags drift (flips {min(f for f in flips if f):.1%}-"
+                         f"{max(f for f in flips if f):.1%} per system), each re-aggregated and re-assembled; "
+                         f"FP64 coarsened solve to rtol {args.rtol:g}; value = median over the systems of their mean "
+                         f"ms per solve, ms_per_step = mean over the {K} timed solves ({per[0]} per system)"),
+            "n_verts": n_v, "n_elems": n_e, "mesh_setup_ms": round(setup_ms, 2), "rtol": args.rtol,
+            "step_ms": spread(all64),
+        },
+        "roofline": roof,
+        "cpu_baseline": None,
+        "solution_error": {"coarse_fp64_max": max(sy["fp64"]["rel_err"] for sy in systems),
+                           "coarse_mixed_max": max(sy["mixed"]["rel_err"] for sy in systems),
+                           "fine_fp64": err_f,
+                           "against": "each system's float64 solve to rtol 1e-12 (coarsened: P A_c^-1 P^T g; "
+                                      "fine: H^-1 g)"},
+        "mixed": {"value_ms": round(medmx, 4), "ms_per_step": round(meanmx, 4), "inner_rtol": args.inner_rtol,
+                  "speedup_vs_fine_fp64": round(ms_fine / medmx, 3), "roofline": roof_mx,
+                  "step_ms": spread([v for s in msmx for v in s])},
+        "fine_fp64": {"ms_per_solve": round(ms_fine, 4), "rtol": args.rtol_fine, "pcg_iters": finfo.pcg_iters,
+                      "steps": kf, "roofline": roof_f},
+        "speedup_vs_fine_fp64": round(ms_fine / med64, 3),
+        "systems": systems,
+    }
+    if f32in is not None:
+        out["f32_element_input_system0"] = f32in
+    refs.clear()
+    del probs, tags, eh, g, rest, edges, x, mp, ref_fine
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline: the oracle on a slab of system 0")
+        full = {"nnzb": int(systems[0]["nnzb_coarse"]), "iters": int(systems[0]["fp64"]["pcg_iters"])}
+        out["cpu_baseline"] = cpu_baseline_slab(p, tag_np[0], args.rtol, args.cpu_layers, full)
+        log(f"[bench]   {out['cpu_baseline']['value']} ms ({out['cpu_baseline']['sample']})")
+    else:
+        del out["cpu_baseline"]
+    return out
+
+
+# ------------------------------------------------------------ a single system (c1 .. c4)
 
 def newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth):
     """One implicit time step's Newton loop (no contact): the coarsened loop
@@ -151,15 +404,15 @@ def newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth):
         opts = agc.make_newton_opts(eps_d=1e-3 * diag, coarsen=coarsen, solve=so)
         x_out = torch.empty_like(x_t)
         ms, info = time_steps(lambda: agc.agc_newton_step(ctx, nw, opts, x_t, v_t, f, x_out)[1],
-                              max(2, args.steps // 3), 1, torch)
-        res[name] = {"ms_per_time_step": round(ms, 3), "newton_iters": info.newton_iters,
+                              max(2, args.steps // 6), 1, torch)
+        res[name] = {"ms_per_time_step": round(float(np.mean(ms)), 3), "newton_iters": info.newton_iters,
                      "pcg_iters": info.pcg_iters, "halvings": info.halvings,
                      "mean_coarse_nodes": round(info.coarse_nodes_sum / max(info.newton_iters, 1), 1),
                      "energy0": info.energy0, "energy": info.energy,
                      "ms_phases": {"physics": round(info.ms_physics, 3), "tags": round(info.ms_tags, 3),
                                    "solve": round(info.ms_solve, 3), "line_search": round(info.ms_line, 3)}}
-        log(f"[bench] Newton time step, {name}: {ms:.2f} ms, {info.newton_iters} iterations, "
-            f"{info.pcg_iters} PCG iterations, mean coarse size {res[name]['mean_coarse_nodes']:.0f}, "
+        log(f"[bench] Newton time step, {name}: {res[name]['ms_per_time_step']:.2f} ms, {info.newton_iters} "
+            f"iterations, {info.pcg_iters} PCG iterations, mean coarse size {res[name]['mean_coarse_nodes']:.0f}, "
             f"E {info.energy0:.6g} -> {info.energy:.8g}")
     nw.close()
     drop = res["fine"]["energy0"] - res["fine"]["energy"]
@@ -168,45 +421,6 @@ def newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth):
         res[k]["energy_gap_vs_fine"] = (res[k]["energy"] - res["fine"]["energy"]) / drop if drop > 0 else None
     res["eps_d"] = 1e-3 * diag
     return res
-
-
-def extras(args, p, ctx, mesh, edges, tags, ev, t, solver, extra, torch, agc, synth):
-    """The rows reported beside the metric: post-coarsening, affine embedding,
-    edge tagging and one Newton time step."""
-    # the step after prolongation: post-coarsening, 10 fine PCG iterations (reported beside the metric)
-    post = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, post_iters=10)
-    ms_post, pinfo = time_steps(post, max(3, args.steps // 2), 1, torch)
-    log(f"[bench] with post-coarsening (10 fine PCG iterations): {ms_post:.3f} ms/solve, fine residual "
-        f"{pinfo.fine_rel_res0:.2e} -> {pinfo.fine_rel_res:.2e}")
-    extra["post_coarsening"] = {"iters": pinfo.post_iters, "ms_per_solve": round(ms_post, 4),
-                                "fine_rel_res_before": pinfo.fine_rel_res0, "fine_rel_res_after": pinfo.fine_rel_res}
-    # the paper's main variant: 12-DoF affine nodes for aggregates of more than 32 vertices
-    aff = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, affine_threshold=32)
-    ms_aff, ainfo = time_steps(aff, max(3, args.steps // 2), 1, torch)
-    log(f"[bench] with affine embedding (> 32 members): {ms_aff:.3f} ms/solve, {ainfo.n_affine} affine nodes, "
-        f"{ainfo.n_blocks} block rows, pcg_iters={ainfo.pcg_iters} rel_res={ainfo.rel_res:.2e}")
-    extra["affine_embedding"] = {"threshold": 32, "ms_per_solve": round(ms_aff, 4), "n_affine": ainfo.n_affine,
-                                 "block_rows": ainfo.n_blocks, "pcg_iters": ainfo.pcg_iters,
-                                 "rel_res_fp64": ainfo.rel_res}
-    # the step before the map: Green-strain-increment tags for two synthetic iterates
-    n_tets = int(p.get("n_tets", p["elem_verts"].shape[0]))
-    tagger = agc.agc_tagger_create(ctx, p["n_verts"], ev[:n_tets].contiguous(), t(p["pos"], torch.float64), edges)
-    xp, xc = synth.deformation_states(p)
-    xp, xc = t(xp, torch.float64), t(xc, torch.float64)
-    tag_out = torch.empty_like(tags)
-
-    def tag_step():
-        agc.agc_tag_edges(ctx, tagger, xc, xp, 5e-5, tag_out, count=False)
-        return None
-    ms_tag, _ = time_steps(tag_step, max(args.steps, 10), 2, torch)
-    _, n_prot = agc.agc_tag_edges(ctx, tagger, xc, xp, 5e-5, tag_out)
-    tagger.close()
-    log(f"[bench] edge tags (Green strain increment, 5e-5): {ms_tag:.3f} ms, {n_prot / tag_out.numel():.3f} protected")
-    extra["tag_ms_per_call"] = round(ms_tag, 4)
-    extra["tag_protected_fraction"] = round(n_prot / tag_out.numel(), 4)
-    if "n_tets" not in p:   # the outer Newton loop and the adjoint's element blocks need a pure tetrahedral mesh
-        extra["adjoint"] = adjoint_step(args, p, ctx, mesh, edges, tags, t, torch, agc, synth)
-        extra["newton"] = newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth)
 
 
 def adjoint_step(args, p, ctx, mesh, edges, tags, t, torch, agc, synth):
@@ -230,16 +444,16 @@ def adjoint_step(args, p, ctx, mesh, edges, tags, t, torch, agc, synth):
 
     def bwd():
         return agc.agc_solve_backward(ctx, prob, opts, mp, box["info"].n_coarse, x, w, dg, dh)
-    reps = max(3, args.steps // 2)
+    reps = max(3, args.steps // 4)
     ms_f, finfo = time_steps(fwd, reps, 1, torch)
     ms_b, binfo = time_steps(bwd, reps, 1, torch)
     L = float((w * x).sum())
     lin = float((dg * g).sum())
     euler = float((dh * eh).sum())
-    log(f"[bench] adjoint (FP64, rtol 1e-12): forward {ms_f:.3f} ms ({finfo.pcg_iters} iters), backward "
-        f"{ms_b:.3f} ms ({binfo.pcg_iters} iters); identities {abs(lin - L) / abs(L):.1e}, "
+    log(f"[bench] adjoint (FP64, rtol 1e-12): forward {np.mean(ms_f):.3f} ms ({finfo.pcg_iters} iters), backward "
+        f"{np.mean(ms_b):.3f} ms ({binfo.pcg_iters} iters); identities {abs(lin - L) / abs(L):.1e}, "
         f"{abs(euler + L) / abs(L):.1e}")
-    out = {"rtol": 1e-12, "forward_ms": round(ms_f, 4), "backward_ms": round(ms_b, 4),
+    out = {"rtol": 1e-12, "forward_ms": round(float(np.mean(ms_f)), 4), "backward_ms": round(float(np.mean(ms_b)), 4),
            "forward_pcg_iters": finfo.pcg_iters, "backward_pcg_iters": binfo.pcg_iters,
            "dH_bytes": n_e * 144 * 8,
            "rel_err_linearity": abs(lin - L) / abs(L), "rel_err_homogeneity": abs(euler + L) / abs(L)}
@@ -248,103 +462,213 @@ def adjoint_step(args, p, ctx, mesh, edges, tags, t, torch, agc, synth):
     return out
 
 
-N_DRIFT_SYSTEMS = 10
+def f32_element_input(args, p, ctx, mesh, edges, tags, eh, g, ref, rtol, torch, agc):
+    """The mixed variant that takes the element blocks in float32 (cast outside
+    the timed region) and sums the coarse matrix in float32.  Measured: the
+    float32 coarse assembly against the float64 one, and the error of the
+    solution of the float32-summed matrix against the float64 reference.  A
+    float64 residual still needs the float64 matrix, so this variant adds the
+    float32 assembly to every solve instead of rounding the float64 sums."""
+    n = p["n_verts"]
+    eh32 = eh.to(torch.float32)
+    mp, nc = agc.agc_aggregate(ctx, n, edges, tags)
+    reps = max(3, args.steps // 4)
+
+    def asm(blocks, out_dtype):
+        a, gc = agc.agc_assemble_coarse(ctx, mesh, blocks, g, mp, nc, out_dtype=out_dtype)
+        return a, gc
+    ms32, (a32, g_c) = time_steps(lambda: asm(eh32, agc.AGC_F32), reps, 1, torch)
+    ms64, (a64, _) = time_steps(lambda: asm(eh, agc.AGC_F64), reps, 1, torch)
+    x_c = torch.zeros_like(g_c)
+    info = agc.agc_pcg(ctx, a32, g_c, x_c, 1e-7, 50000, raise_on_not_converged=False)
+    x = agc.agc_prolongate(ctx, mp, nc, x_c)
+    err = float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
+    out = {"assemble_f32_from_f32_ms": round(float(np.mean(ms32)), 4),
+           "assemble_f64_from_f64_ms": round(float(np.mean(ms64)), 4),
+           "f32_summed_matrix_solution_rel_err": err, "f32_summed_matrix_pcg_iters": info.iters,
+           "note": "float32 sums of float32 element blocks, solved to rtol 1e-7 without float64 refinement; "
+                   "a float64 residual would need the float64 matrix as well"}
+    log(f"[bench] f32 element input: assembly f32 {out['assemble_f32_from_f32_ms']:.3f} ms vs f64 "
+        f"{out['assemble_f64_from_f64_ms']:.3f} ms; error of the f32-summed matrix's solution {err:.2e}")
+    a32.close()
+    a64.close()
+    del eh32
+    torch.cuda.empty_cache()
+    return out
 
 
-def drift_systems(args, p, ctx, prob, tags, x, mp, setup_ms, torch, agc, synth):
-    """A sequence of systems on one mesh whose tags drift (about 10% flip per
-    system): every solve re-aggregates, re-assembles, solves and prolongates.
-    Reported: per-system ms of the mixed solve (the value is their median), the
-    flip fractions, coarse sizes, GB/s of the assembly and of the PCG SpMV, and
-    the fine FP64 comparator (the same for every system: it does not use tags)."""
-    mixed_kw = dict(rtol=args.rtol, precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol)
-    steps = max(1, min(args.steps, 5))
+def extras(args, p, ctx, mesh, edges, tags, ev, t, solver, extra, torch, agc, synth):
+    """The rows reported beside the metric: post-coarsening, affine embedding,
+    edge tagging, the adjoint and one Newton time step."""
+    reps = max(3, args.steps // 4)
+    post = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, post_iters=10)
+    ms_post, pinfo = time_steps(post, reps, 1, torch)
+    log(f"[bench] with post-coarsening (10 fine PCG iterations): {np.mean(ms_post):.3f} ms/solve, fine residual "
+        f"{pinfo.fine_rel_res0:.2e} -> {pinfo.fine_rel_res:.2e}")
+    extra["post_coarsening"] = {"iters": pinfo.post_iters, "ms_per_solve": round(float(np.mean(ms_post)), 4),
+                                "fine_rel_res_before": pinfo.fine_rel_res0, "fine_rel_res_after": pinfo.fine_rel_res}
+    aff = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, affine_threshold=32)
+    ms_aff, ainfo = time_steps(aff, reps, 1, torch)
+    log(f"[bench] with affine embedding (> 32 members): {np.mean(ms_aff):.3f} ms/solve, {ainfo.n_affine} affine "
+        f"nodes, {ainfo.n_blocks} block rows, pcg_iters={ainfo.pcg_iters} rel_res={ainfo.rel_res:.2e}")
+    extra["affine_embedding"] = {"threshold": 32, "ms_per_solve": round(float(np.mean(ms_aff)), 4),
+                                 "n_affine": ainfo.n_affine, "block_rows": ainfo.n_blocks,
+                                 "pcg_iters": ainfo.pcg_iters, "rel_res_fp64": ainfo.rel_res}
+    n_tets = int(p.get("n_tets", p["elem_verts"].shape[0]))
+    tagger = agc.agc_tagger_create(ctx, p["n_verts"], ev[:n_tets].contiguous(), t(p["pos"], torch.float64), edges)
+    xp, xc = synth.deformation_states(p)
+    xp, xc = t(xp, torch.float64), t(xc, torch.float64)
+    tag_out = torch.empty_like(tags)
 
-    def solve(**kw):
-        return agc.agc_solve(ctx, prob, agc.make_opts(**kw), x, mp)
+    def tag_step():
+        agc.agc_tag_edges(ctx, tagger, xc, xp, 5e-5, tag_out, count=False)
+        return None
+    ms_tag, _ = time_steps(tag_step, max(args.steps, 10), 2, torch)
+    _, n_prot = agc.agc_tag_edges(ctx, tagger, xc, xp, 5e-5, tag_out)
+    tagger.close()
+    log(f"[bench] edge tags (Green strain increment, 5e-5): {np.mean(ms_tag):.3f} ms, "
+        f"{n_prot / tag_out.numel():.3f} protected")
+    extra["tag_ms_per_call"] = round(float(np.mean(ms_tag)), 4)
+    extra["tag_protected_fraction"] = round(n_prot / tag_out.numel(), 4)
+    if "n_tets" not in p:   # the outer Newton loop and the adjoint's element blocks need a pure tetrahedral mesh
+        extra["adjoint"] = adjoint_step(args, p, ctx, mesh, edges, tags, t, torch, agc, synth)
+        extra["newton"] = newton_step(args, p, ctx, mesh, edges, t, torch, agc, synth)
 
-    def rel(ref):
+
+PAPER_ROW_BODIES = 96
+SINGLE_RTOL = {"c1": (1e-10, 1e-10), "c2": (4e-7, 1e-6), "c3": (1e-7, 1e-7), "c4": (4e-7, 1e-6)}
+
+
+def single_system(args, name, ctx, torch, agc, synth, with_extras, headline):
+    """One system: FP64 coarsened (the value), mixed coarsened and fine FP64 solves."""
+    log(f"[bench] generating {name}")
+    t0 = time.perf_counter()
+    p = synth.make_config(name, log=lambda m: log(f"[bench]   {m} ({time.perf_counter() - t0:.0f}s)"))
+    dev = ctx.device
+
+    def t(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)
+
+    rtol, rtol_fine = SINGLE_RTOL[name] if not headline else (args.rtol, args.rtol_fine)
+    edges, tags = t(p["edges"], torch.int32), t(p["tags"], torch.uint8)
+    ev, eh, g = t(p["elem_verts"], torch.int32), t(p["elem_H"], torch.float64), t(p["g"], torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mesh = agc.agc_mesh_create(ctx, p["n_verts"], ev)
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    prob = agc.make_problem(mesh, edges, tags, eh, g, t(p["pos"], torch.float64))
+    x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=dev)
+    mp = torch.empty(p["n_verts"], dtype=torch.int32, device=dev)
+
+    def solver(rtol=rtol, **kw):
+        o = agc.make_opts(rtol=rtol, max_iter=50000, **kw)
+
+        def run():
+            return agc.agc_solve(ctx, prob, o, x, mp)
+        return run
+
+    def rel_err(run, ref):
+        run()
+        torch.cuda.synchronize()
         return float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
 
-    n_e, n_v = int(p["elem_verts"].shape[0]), int(p["n_verts"])
-    systems, prev, ti = [], None, None
-    for it in range(N_DRIFT_SYSTEMS):
-        tg = synth.drift_tags(p, it)
-        flip = None if prev is None else round(float(np.mean(tg != prev)), 4)
-        prev = tg
-        tags.copy_(torch.from_numpy(tg))
-        torch.cuda.synchronize()
-        solve(rtol=1e-12, max_iter=50000)
-        ref = x.clone()
-        ms, info = time_steps(lambda: solve(**mixed_kw), steps, 1, torch)
-        err = rel(ref)
-        ph = solve(timing=1, **mixed_kw)
-        asm_bytes = n_e * (16 + 144 * 8) + n_v * (24 + 4) + int(info.nnzb) * (9 * 8 + 4)
-        systems.append({"system": it, "ms": round(ms, 3), "flip_fraction": flip, "n_coarse": info.n_coarse,
-                        "nnzb_coarse": int(info.nnzb), "pcg_iters": info.pcg_iters,
-                        "rel_err_vs_fp64": err,
-                        "phase_ms": {"aggregate": round(ph.ms_aggregate, 3), "assemble": round(ph.ms_assemble, 3),
-                                     "pcg": round(ph.ms_pcg, 3), "prolong": round(ph.ms_prolong, 3)},
-                        "assembly_gbs": round(asm_bytes / (ph.ms_assemble * 1e-3) / 1e9, 1)})
-        log(f"[bench] system {it}: {ms:.2f} ms, flips {flip}, n_c={info.n_coarse} nnzb={info.nnzb} "
-            f"pcg_iters={info.pcg_iters} err={err:.2e}")
-        if it == 0:
-            ti = solve(timing=2, **mixed_kw)
-    spmv_avg_ms = ti.ms_spmv / max(ti.spmv_launches, 1)
-    spmv_alg = spmv_bytes(ti.nnzb, ti.n_coarse, 4)
-    achieved = spmv_alg / (spmv_avg_ms * 1e-3) / 1e9
-    solve(rtol=1e-12, max_iter=50000, coarsen=0)
-    ref_f = x.clone()
-    ms_fine, finfo = time_steps(lambda: solve(rtol=args.rtol_fine, coarsen=0), steps, 1, torch)
-    err_f = rel(ref_f)
-    fi = solve(rtol=args.rtol_fine, coarsen=0, timing=2)
-    log(f"[bench] fine FP64 comparator: {ms_fine:.2f} ms, pcg_iters={finfo.pcg_iters} err={err_f:.2e}")
-    per = sorted(sy["ms"] for sy in systems)
-    med = per[len(per) // 2]
-    return {
-        "metric": "ms per Newton linear solve (coarsen+assemble+PCG+prolong) vs fine PCG, 1 GPU",
-        "value": med, "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": med,
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 SpMV values + f64 assembly sums, vectors, dots, residuals", "data": "synthetic",
-        "config": {
-            "workload": (f"{args.config}: cube grid, 5 tets/cube, {n_v} vertices, {n_e} tets, {p['frac']:.0%} "
-                         f"collapsible edges, {N_DRIFT_SYSTEMS} systems with drifting tags, mixed precision, "
-                         f"rtol {args.rtol:g}; value = median over the systems"),
-            "n_verts": n_v, "n_elems": n_e, "mesh_setup_ms": round(setup_ms, 2), "rtol": args.rtol,
-        },
-        "roofline": {
-            "kernel": "k_pcg_spmv<float> (fused SpMV w = A z and z^T w, float32 matrix), system 0",
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_launch_us": round(spmv_avg_ms * 1e3, 3), "launches": ti.spmv_launches,
-            "algorithmic_bytes_per_launch": int(spmv_alg),
-        },
-        "systems": systems,
-        "fine_fp64_ms_per_solve": round(ms_fine, 3), "fine_pcg_iters": finfo.pcg_iters, "fine_rel_err": err_f,
-        "rtol_fine": args.rtol_fine,
-        "speedup_vs_fine_fp64": round(ms_fine / med, 3),
-        "fine_spmv_us": round(fi.ms_spmv / max(fi.spmv_launches, 1) * 1e3, 3),
-        "fine_spmv_gbs": round(spmv_bytes(fi.nnzb, fi.n_coarse, 8) /
-                               (fi.ms_spmv / max(fi.spmv_launches, 1) * 1e-3) / 1e9, 1),
+    solver(rtol=1e-12)()
+    ref_coarse = x.clone()
+    solver(rtol=1e-12, coarsen=0)()
+    ref_fine = x.clone()
+    K, W = (args.steps, args.warmup) if headline else (max(5, args.steps // 2), 2)
+
+    c64 = solver()
+    err_c64 = rel_err(c64, ref_coarse)
+    ms64, info = time_steps(c64, K, W, torch)
+    phs = [agc.agc_solve(ctx, prob, agc.make_opts(rtol=rtol, timing=1, max_iter=50000), x, mp) for _ in range(3)]
+    ph = types.SimpleNamespace(**{k: float(np.median([getattr(q, k) for q in phs]))
+                                  for k in ("ms_aggregate", "ms_assemble", "ms_pcg", "ms_prolong")})
+    ti = agc.agc_solve(ctx, prob, agc.make_opts(rtol=rtol, timing=2, max_iter=50000), x, mp)
+    roof = roofline("k_pcg_spmv<double> (fused SpMV w = A z and z^T w, float64 coarse matrix)", int(ti.nnzb),
+                    ti.n_coarse, 8, 8, ti, measured_traffic(name, "f64"))
+    log(f"[bench] {name} coarsened FP64: {np.mean(ms64):.3f} ms/solve n_c={info.n_coarse} nnzb={info.nnzb} "
+        f"iters={info.pcg_iters} err={err_c64:.2e}; SpMV {roof['avg_launch_us']:.2f} us ({roof['frac']:.3f})")
+
+    mix = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol)
+    err_mx = rel_err(mix, ref_coarse)
+    msmx, minfo = time_steps(mix, K, W, torch)
+    tm = agc.agc_solve(ctx, prob, agc.make_opts(rtol=rtol, precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol,
+                                                timing=2, max_iter=50000), x, mp)
+    roof_mx = roofline("k_pcg_spmv<float> (float32 coarse matrix, float32 z)", int(tm.nnzb), tm.n_coarse, 4, 4, tm,
+                       measured_traffic(name, "f32"))
+    log(f"[bench] {name} coarsened mixed: {np.mean(msmx):.3f} ms/solve iters={minfo.pcg_iters} "
+        f"refine={minfo.refine_iters} err={err_mx:.2e}; SpMV {roof_mx['avg_launch_us']:.2f} us ({roof_mx['frac']:.3f})")
+
+    fine = solver(rtol=rtol_fine, coarsen=0)
+    err_f = rel_err(fine, ref_fine)
+    msf, finfo = time_steps(fine, K, max(1, W // 2), torch)
+    fi = agc.agc_solve(ctx, prob, agc.make_opts(rtol=rtol_fine, coarsen=0, timing=2, max_iter=50000), x, mp)
+    roof_f = roofline("k_pcg_spmv<double> on the fine matrix", int(fi.nnzb), fi.n_coarse, 8, 8, fi, None)
+    log(f"[bench] {name} fine FP64: {np.mean(msf):.3f} ms/solve iters={finfo.pcg_iters} err={err_f:.2e}")
+
+    res = {
+        "coarse_fp64": {"ms_per_solve": round(float(np.mean(ms64)), 4), "step_ms": spread(ms64), "rtol": rtol,
+                        "n_coarse": info.n_coarse, "nnzb_coarse": int(info.nnzb), "pcg_iters": info.pcg_iters,
+                        "rel_res": info.rel_res, "rel_err": err_c64,
+                        "phase_ms": {"aggregate": round(ph.ms_aggregate, 4), "assemble": round(ph.ms_assemble, 4),
+                                     "pcg": round(ph.ms_pcg, 4), "prolong": round(ph.ms_prolong, 4)},
+                        "roofline": roof},
+        "coarse_mixed": {"ms_per_solve": round(float(np.mean(msmx)), 4), "pcg_iters": minfo.pcg_iters,
+                         "refine_iters": minfo.refine_iters, "rel_err": err_mx, "inner_rtol": args.inner_rtol,
+                         "roofline": roof_mx},
+        "fine_fp64": {"ms_per_solve": round(float(np.mean(msf)), 4), "rtol": rtol_fine, "pcg_iters": finfo.pcg_iters,
+                      "rel_err": err_f, "roofline": roof_f},
+        "speedup_fp64_vs_fine_fp64": round(float(np.mean(msf) / np.mean(ms64)), 3),
+        "speedup_mixed_vs_fine_fp64": round(float(np.mean(msf) / np.mean(msmx)), 3),
+        "n_verts": p["n_verts"], "n_elems": int(p["elem_verts"].shape[0]), "mesh_setup_ms": round(setup_ms, 2),
     }
+    if with_extras:
+        res["f32_element_input"] = f32_element_input(args, p, ctx, mesh, edges, tags, eh, g, ref_coarse, rtol, torch,
+                                                     agc)
+        extras(args, p, ctx, mesh, edges, tags, ev, t, solver, res, torch, agc, synth)
+    out = None
+    if headline:
+        if name == "c3":
+            workload = (f"c3: {PAPER_ROW_BODIES} cuboids of 4x8x24 cubes in a row, 5 tets/cube, {p['n_verts']} "
+                        f"vertices, {p['n_tets']} tets + {p['n_contacts']} point-triangle barrier blocks, per-body "
+                        f"collapsible fraction U(0.2, 0.9), FP64 coarsened solve to rtol {rtol:g}")
+        else:
+            workload = (f"{name}: cube grid, 5 tets/cube, {p['n_verts']} vertices, {p['elem_verts'].shape[0]} tets, "
+                        f"{p['frac']:.0%} collapsible edges, FP64 coarsened solve to rtol {rtol:g}")
+        out = {"metric": METRIC, "value": res["coarse_fp64"]["ms_per_solve"], "unit": "ms", "n_gpus": 1,
+               "steps": K, "warmup": W, "ms_per_step": res["coarse_fp64"]["ms_per_solve"],
+               "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic", "config": {"workload": workload, "n_verts": p["n_verts"],
+                                               "n_elems": int(p["elem_verts"].shape[0]), "rtol": rtol,
+                                               "step_ms": spread(ms64)},
+               "roofline": roof}
+        out.update(res)
+        out["speedup_vs_fine_fp64"] = res["speedup_fp64_vs_fine_fp64"]
+        if not args.no_cpu_baseline:
+            log("[bench] CPU baseline: the oracle on the same workload")
+            out["cpu_baseline"] = cpu_baseline_single(p, rtol)
+            log(f"[bench]   {out['cpu_baseline']['value']} ms")
+    mesh.close()
+    return out if headline else res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
-    # tolerances at which each path reaches a 1e-5 relative solution error on c2
-    # (measured against FP64 references solved to 1e-12; both are reported)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
+    # tolerances at which each path reaches a 1e-5 relative solution error at 128^3
+    # (against float64 references solved to 1e-12; both are reported)
     ap.add_argument("--rtol", type=float, default=4e-7, help="coarsened solve tolerance")
-    ap.add_argument("--rtol-fine", type=float, default=1e-6, help="fine FP64 comparator tolerance")
+    ap.add_argument("--rtol-fine", type=float, default=3e-7, help="fine FP64 comparator tolerance")
     ap.add_argument("--inner-rtol", type=float, default=1e-4, help="mixed: tolerance of each inner solve")
+    ap.add_argument("--cpu-layers", type=int, default=24, help="cube layers of the CPU baseline's slab sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the fine and FP64 comparators")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip post-coarsening, affine embedding, tagging and the Newton step (profiling runs: "
-                         "the PCG SpMV then runs on the measured coarse matrix only)")
+                    help="skip the 64^3 grid's figures (post-coarsening, affine embedding, tagging, adjoint, Newton "
+                         "step; with --config c1..c4 those of that system)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates the HBM counters), then exit")
     args = ap.parse_args()
@@ -368,153 +692,36 @@ def main():
 
     from paper_2605_04773_amd import agc, synth
 
-    log(f"[bench] generating {args.config}")
+    ctx = agc.Context(0)
+    if args.config != "c5":
+        out = single_system(args, args.config, ctx, torch, agc, synth, not args.no_extras, True)
+        print(json.dumps(out), flush=True)
+        ctx.close()
+        return
+
+    log("[bench] generating c5")
     t0 = time.perf_counter()
-    p = synth.make_config(args.config, log=lambda m: log(f"[bench]   {m} ({time.perf_counter() - t0:.0f}s)"))
+    p = synth.make_config("c5", log=lambda m: log(f"[bench]   {m} ({time.perf_counter() - t0:.0f}s)"))
     log(f"[bench] generated in {time.perf_counter() - t0:.1f}s: {p['n_verts']} vertices, "
         f"{p['elem_verts'].shape[0]} elements, {p['edges'].shape[0]} edges")
-    dev = torch.device("cuda", 0)
+    dev = ctx.device
 
     def t(a, dt):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)
 
-    ctx = agc.Context(0)
-    edges, tags = t(p["edges"], torch.int32), t(p["tags"], torch.uint8)
-    ev, eh, g = t(p["elem_verts"], torch.int32), t(p["elem_H"], torch.float64), t(p["g"], torch.float64)
+    ev = t(p["elem_verts"], torch.int32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mesh = agc.agc_mesh_create(ctx, p["n_verts"], ev)
     setup_ms = (time.perf_counter() - t0) * 1e3
     log(f"[bench] mesh setup (static, once per mesh) {setup_ms:.1f} ms")
-    prob = agc.make_problem(mesh, edges, tags, eh, g, t(p["pos"], torch.float64))
-    x = torch.empty((p["n_verts"], 3), dtype=torch.float64, device=dev)
-    mp = torch.empty(p["n_verts"], dtype=torch.int32, device=dev)
-
-    if "drift_delta" in p:
-        out = drift_systems(args, p, ctx, prob, tags, x, mp, setup_ms, torch, agc, synth)
-        print(json.dumps(out), flush=True)
-        mesh.close()
-        ctx.close()
-        return
-
-    def solver(rtol=args.rtol, **kw):
-        o = agc.make_opts(rtol=rtol, **kw)
-
-        def run():
-            return agc.agc_solve(ctx, prob, o, x, mp)
-        return run
-
-    def rel_err(run, ref):
-        run()
-        torch.cuda.synchronize()
-        return float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
-
-    # FP64 references to rtol 1e-12 (outside the timed region) for the error report
-    solver(rtol=1e-12, max_iter=50000)()
-    ref_coarse = x.clone()
-    solver(rtol=1e-12, max_iter=50000, coarsen=0)()
-    ref_fine = x.clone()
-
-    mixed = solver(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol)
-    err_mixed = rel_err(mixed, ref_coarse)
-    log("[bench] coarsened mixed-precision solve")
-    ms_mixed, info = time_steps(mixed, args.steps, args.warmup, torch, key="mixed")
-    log(f"[bench]   {ms_mixed:.3f} ms/solve  n_c={info.n_coarse} nnzb={info.nnzb} "
-        f"pcg_iters={info.pcg_iters} refine={info.refine_iters} rel_res={info.rel_res:.2e}")
-
-    # phase split (HIP events around the phases), then the live duration of the
-    # fused PCG SpMV: after each PCG solve the library replays that kernel 20
-    # times back to back between two HIP events on its stream
-    # the split is the per-phase median of three solves (one solve's PCG phase
-    # includes host round trips, which a stall of the host can lengthen)
-    phs = [agc.agc_solve(ctx, prob, agc.make_opts(rtol=args.rtol, precision=agc.AGC_PREC_MIXED,
-                                                  inner_rtol=args.inner_rtol, timing=1), x, mp) for _ in range(3)]
-    ph = types.SimpleNamespace(**{k: float(np.median([getattr(q, k) for q in phs]))
-                                  for k in ("ms_aggregate", "ms_assemble", "ms_pcg", "ms_prolong")})
-    ti = agc.agc_solve(ctx, prob, agc.make_opts(rtol=args.rtol, precision=agc.AGC_PREC_MIXED,
-                                                inner_rtol=args.inner_rtol, timing=2), x, mp)
-    spmv_avg_ms = ti.ms_spmv / max(ti.spmv_launches, 1)
-    spmv_alg = spmv_bytes(ti.nnzb, ti.n_coarse, 4)
-    achieved = spmv_alg / (spmv_avg_ms * 1e-3) / 1e9
-    log(f"[bench]   phases ms: aggregate {ph.ms_aggregate:.3f} assemble {ph.ms_assemble:.3f} "
-        f"pcg {ph.ms_pcg:.3f} prolong {ph.ms_prolong:.3f}; PCG SpMV {spmv_avg_ms * 1e3:.2f} us x "
-        f"{ti.spmv_launches} = {achieved:.0f} GB/s")
-
-    extra = {"solution_error": {"coarse_mixed": err_mixed}}
-    if not args.no_extras:
-        extras(args, p, ctx, mesh, edges, tags, ev, t, solver, extra, torch, agc, synth)
-    if not args.no_compare:
-        log("[bench] fine FP64 solve (comparator)")
-        fine = solver(rtol=args.rtol_fine, coarsen=0)
-        err_fine = rel_err(fine, ref_fine)
-        ms_fine, finfo = time_steps(fine, args.steps, max(1, args.warmup // 2), torch)
-        log(f"[bench]   {ms_fine:.3f} ms/solve  pcg_iters={finfo.pcg_iters} rel_res={finfo.rel_res:.2e} "
-            f"err={err_fine:.2e}")
-        log("[bench] coarsened FP64 solve")
-        c64 = solver()
-        err_c64 = rel_err(c64, ref_coarse)
-        ms_c64, cinfo = time_steps(c64, args.steps, max(1, args.warmup // 2), torch)
-        log(f"[bench]   {ms_c64:.3f} ms/solve  pcg_iters={cinfo.pcg_iters} rel_res={cinfo.rel_res:.2e} "
-            f"err={err_c64:.2e}")
-        fi = agc.agc_solve(ctx, prob, agc.make_opts(rtol=args.rtol_fine, coarsen=0, timing=2), x, mp)
-        extra["solution_error"].update({"fine_fp64": err_fine, "coarse_fp64": err_c64})
-        extra.update({
-            "fine_fp64_ms_per_solve": round(ms_fine, 4),
-            "coarse_fp64_ms_per_solve": round(ms_c64, 4),
-            "speedup_vs_fine_fp64": round(ms_fine / ms_mixed, 3),
-            "rtol_fine": args.rtol_fine,
-            "fine_pcg_iters": finfo.pcg_iters,
-            "coarse_fp64_pcg_iters": cinfo.pcg_iters,
-            "fine_spmv_us": round(fi.ms_spmv / max(fi.spmv_launches, 1) * 1e3, 3),
-            "fine_spmv_gbs": round(spmv_bytes(fi.nnzb, fi.n_coarse, 8) /
-                                   (fi.ms_spmv / max(fi.spmv_launches, 1) * 1e-3) / 1e9, 1),
-        })
-
-    if p["name"] == "c3":
-        workload = (f"c3: {PAPER_ROW_BODIES} cuboids of 4x8x24 cubes in a row, 5 tets/cube, {p['n_verts']} vertices, "
-                    f"{p['n_tets']} tets + {p['n_contacts']} point-triangle barrier blocks, per-body collapsible "
-                    f"fraction U(0.2, 0.9), mixed precision, rtol {args.rtol:g}")
-    else:
-        workload = (f"{args.config}: cube grid, 5 tets/cube, {p['n_verts']} vertices, {p['elem_verts'].shape[0]} tets, "
-                    f"{p['frac']:.0%} collapsible edges, mixed precision, rtol {args.rtol:g}")
-    out = {
-        "metric": "ms per Newton linear solve (coarsen+assemble+PCG+prolong) vs fine PCG, 1 GPU",
-        "value": round(ms_mixed, 4),
-        "unit": "ms",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_mixed, 4),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 SpMV values + f64 assembly sums, vectors, dots, residuals",
-        "data": "synthetic",
-        "config": {
-            "workload": workload,
-            "n_verts": p["n_verts"], "n_elems": int(p["elem_verts"].shape[0]),
-            "n_coarse": info.n_coarse, "nnzb_coarse": int(info.nnzb), "pcg_iters": info.pcg_iters,
-            "refine_iters": info.refine_iters, "rel_res_fp64": info.rel_res, "rtol": args.rtol,
-            "mesh_setup_ms": round(setup_ms, 2),
-            "step_ms": spread(STEP_MS["mixed"]),
-            "phase_ms": {"aggregate": round(ph.ms_aggregate, 4), "assemble": round(ph.ms_assemble, 4),
-                         "pcg": round(ph.ms_pcg, 4), "prolong": round(ph.ms_prolong, 4)},
-        },
-        "roofline": {
-            "kernel": "k_pcg_spmv<float> (fused SpMV w = A z and z^T w, float32 matrix)",
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config),
-            "avg_launch_us": round(spmv_avg_ms * 1e3, 3), "launches": ti.spmv_launches,
-            "algorithmic_bytes_per_launch": int(spmv_alg),
-        },
-    }
-    out.update(extra)
-    if not args.no_cpu_baseline:
-        log("[bench] CPU baseline: the oracle on the same workload")
-        out["cpu_baseline"] = cpu_baseline(p, args.rtol)
-        log(f"[bench]   {out['cpu_baseline']['value']} ms")
-    print(json.dumps(out), flush=True)
+    out = drift_systems(args, p, ctx, mesh, dev, t, torch, agc, synth, setup_ms)
     mesh.close()
+    del ev, p
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["c2"] = single_system(args, "c2", ctx, torch, agc, synth, True, False)
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 
