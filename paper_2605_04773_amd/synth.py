@@ -27,6 +27,7 @@ directions, 5 jitter, 6 contact, 7 drift, 8 deformation states.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 
@@ -157,25 +158,41 @@ def random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
     return r
 
 
-def elastic_blocks(pos, tets, rot, mu, lam, rho, h, out=None, chunk=1 << 17, progress=None):
+def elastic_blocks(pos, tets, rot, mu, lam, rho, h, out=None, chunk=1 << 11, progress=None, workers=None):
     """12x12 row-major element blocks (DoF order 3a+k): R K0 R^T + rho V/(4 h^2) I, symmetrised.
 
-    ``progress(done, total)`` is called after every 16 chunks, when given."""
+    Chunks of elements are independent (the rotations are drawn beforehand),
+    so they are computed on a pool of threads; the result does not depend on
+    the pool.  ``progress(done, total)`` is called after every 1024 chunks, when given."""
+    from concurrent.futures import ThreadPoolExecutor
     n = tets.shape[0]
     if out is None:
         out = np.empty((n, 144), dtype=np.float64)
-    for ci, s in enumerate(range(0, n, chunk)):
-        if progress is not None and ci % 16 == 0 and ci > 0:
-            progress(s, n)
+
+    def one(s):
         e = slice(s, min(n, s + chunk))
         vol, grads = shape_gradients(pos, tets[e])
-        k0 = linear_stiffness(vol, grads, mu, lam)                     # (m,4,4,3,3)
-        r = rot[e][:, None, None]
-        kr = r @ k0 @ np.swapaxes(r, -1, -2)
-        blk = kr.transpose(0, 1, 3, 2, 4).reshape(-1, 12, 12)
-        blk += (rho * vol / (4.0 * h * h))[:, None, None] * np.eye(12)
+        # R K0 R^T from the rotated gradients q_a = R grad N_a (R R^T = I):
+        # block (a,b) = V (mu (grad N_a . grad N_b) I + mu q_b q_a^T + lam q_a q_b^T)
+        q = grads @ np.swapaxes(rot[e], -1, -2)                        # (m,4,3)
+        gg = grads @ np.swapaxes(grads, -1, -2)                        # (m,4,4)
+        blk = (mu * q.transpose(0, 2, 1)[:, None, :, :, None]) * q[:, :, None, None, :]
+        blk += (lam * q)[:, :, :, None, None] * q[:, None, None, :, :]
+        idx = np.arange(3)
+        blk[:, :, idx, :, idx] += mu * gg[None]                        # (3,m,4,4) on the k = l diagonal
+        blk *= vol[:, None, None, None, None]
+        blk = blk.reshape(-1, 12, 12)
+        blk[:, np.arange(12), np.arange(12)] += (rho * vol / (4.0 * h * h))[:, None]
         blk = 0.5 * (blk + np.swapaxes(blk, 1, 2))
         out[e] = blk.reshape(-1, 144)
+
+    starts = list(range(0, n, chunk))
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        for ci, _ in enumerate(ex.map(one, starts)):
+            if progress is not None and ci % 1024 == 0 and ci > 0:
+                progress(starts[ci], n)
     return out
 
 
