@@ -5,10 +5,10 @@
 // plus group prefix sum (Alg. 2, Sec. 1.3) orders them by their smallest fine
 // id.  The paper finds components with 32-bit in-warp hash masks applied
 // level by level.  On gfx950 a parent forest does the same job for any
-// component size: every vertex first points at its smallest collapsible
-// neighbour, a few rounds of minimum-label hooking of roots with path
-// flattening merge the trees, and a final edge-parallel pass of lock-free
-// union-find guarantees that every edge ends inside one tree.  A pointer
+// component size, in two passes: each block of consecutive vertex ids is
+// resolved by union-find in one workgroup's LDS (the paper's in-group
+// merge, with groups of 4096 instead of 32 vertices), then the edges between
+// blocks are joined by lock-free union-find on the global forest.  A pointer
 // only ever moves to a smaller vertex of the same component, so the
 // surviving root of every component is its smallest vertex whatever the
 // order of the races.  Flagging the roots and an exclusive scan then give
@@ -48,12 +48,142 @@ __global__ void k_cc_init(int32_t* __restrict__ parent, int32_t n) {
     parent[v] = (int32_t)v;
 }
 
-// Pre-linking: every vertex points at its smallest neighbour over a
-// collapsible edge (if smaller than itself).  The atomics of one vertex
-// number its lower neighbours only, so they barely contend, and afterwards
-// most edges of a component already lead to one root.  Also validates.
-__global__ void k_cc_link_min(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
-                              int32_t* parent, int32_t n, unsigned* err) {
+// ---------------------------------------------------------------- blocks
+//
+// The vertices are cut into blocks of kCcBlock consecutive ids.  Pass one
+// gives each block to one workgroup, which joins the collapsible edges with
+// both ends in its block by union-find in LDS and writes every vertex's
+// local root (the smallest id of its local component) as its parent: no
+// global atomics, and the global forest starts with depth one.  Pass two
+// reads every edge and hooks, with global compare-and-swap, only those the
+// first pass did not join.  With a mesh's edge list ordered by smaller end
+// (as a sorted, deduplicated list is) the first pass takes each block's
+// edges as one contiguous range and the second pass joins few trees: the
+// local components of a block are mostly whole cross-sections of the
+// collapsible regions.  Any order is still correct: the ranges cover every
+// edge, and an edge the first pass cannot join locally is joined by the
+// second.
+
+constexpr int kCcBlock = 4096;          // vertices per block (16 KB of LDS)
+constexpr int kCcLog = 12;
+static_assert((1 << kCcLog) == kCcBlock, "block size");
+constexpr int kCcThreads = 1024;        // threads of a block's workgroup
+
+__device__ __forceinline__ int32_t edge_key(const int32_t* edges, int64_t e) {
+  const int2 uv = reinterpret_cast<const int2*>(edges)[e];
+  return uv.x < uv.y ? uv.x : uv.y;
+}
+
+// First edge index whose smaller end is >= target, for edges ordered by
+// smaller end; one wave probes 64 positions per step (four steps for 16 M
+// edges).  For an unordered list it returns some index in [0, m].
+__device__ int64_t wave_lower_bound(const int32_t* edges, int64_t m, int32_t target) {
+  const unsigned lane = lane_id();
+  int64_t lo = 0, hi = m;                 // the answer lies in [lo, hi]
+  while (hi - lo > kWave) {
+    const int64_t span = hi - lo;
+    const int64_t p = lo + span * (lane + 1) / (kWave + 1);
+    const bool less = edge_key(edges, p) < target;
+    const int c = __popcll(__ballot(less));
+    const int64_t nlo = (c > 0) ? lo + span * c / (kWave + 1) + 1 : lo;
+    const int64_t nhi = (c < kWave) ? lo + span * (c + 1) / (kWave + 1) : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  const int64_t p = lo + lane;
+  const bool less = p < hi && edge_key(edges, p) < target;
+  return lo + __popcll(__ballot(less));
+}
+
+__device__ __forceinline__ int32_t lds_ld(int32_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(int32_t* a, int32_t x) {
+  __hip_atomic_store(a, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Root of x in the block's LDS forest with path halving (x points at its
+// grandparent as the walk passes).  Invariant: lp[x] <= x, roots lp[x] == x,
+// and a stored value is always an ancestor of its node.
+__device__ int32_t lds_find(int32_t* lp, int32_t x) {
+  for (;;) {
+    const int32_t p = lds_ld(lp + x);
+    if (p == x) return x;
+    const int32_t gp = lds_ld(lp + p);
+    if (gp == p) return p;
+    lds_st(lp + x, gp);
+    x = gp;
+  }
+}
+
+// Union of a and b: the larger root is hooked below the smaller, so every
+// local root is the smallest slot of its tree.
+__device__ void lds_union(int32_t* lp, int32_t a, int32_t b) {
+  for (;;) {
+    a = lds_find(lp, a);
+    b = lds_find(lp, b);
+    if (a == b) return;
+    const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    int32_t expect = hi;
+    if (__hip_atomic_compare_exchange_strong(lp + hi, &expect, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+      return;
+    a = lo;           // hi was hooked meanwhile: continue from its new parent
+    b = expect;
+  }
+}
+
+// Pass one.  Workgroup b: vertices [b W, b W + W), edges
+// [min(a_b, a_b+1), max(a_b, a_b+1)) with a_b the first edge whose smaller
+// end is >= b W.  Writes parent[] of its vertices and bounds[b] (and
+// bounds[nb] = m from the last block).  Malformed edges are skipped here and
+// reported by pass two.
+__global__ __launch_bounds__(kCcThreads) void k_cc_local(const int32_t* __restrict__ edges,
+                                                         const uint8_t* __restrict__ tags, int64_t m, int32_t n,
+                                                         int32_t* __restrict__ parent, int64_t* __restrict__ bounds) {
+  __shared__ int32_t lp[kCcBlock];
+  __shared__ int64_t rng[2];
+  const int32_t nb = (int32_t)(((int64_t)n + kCcBlock - 1) >> kCcLog);
+  const int32_t b = blockIdx.x;
+  const int32_t v0 = b << kCcLog;
+  const unsigned wave = threadIdx.x / kWave;
+  if (wave < 2) {
+    const int32_t blk = b + (int32_t)wave;
+    int64_t a;
+    if (blk == 0) a = 0;
+    else if (blk >= nb) a = m;
+    else a = wave_lower_bound(edges, m, blk << kCcLog);
+    if (lane_id() == 0) rng[wave] = a;
+  }
+  for (int i = threadIdx.x; i < kCcBlock; i += kCcThreads) lp[i] = i;
+  __syncthreads();
+  const int64_t a0 = rng[0], a1 = rng[1];
+  if (threadIdx.x == 0) {
+    bounds[b] = a0;
+    if (b == nb - 1) bounds[nb] = m;
+  }
+  const int64_t e0 = a0 < a1 ? a0 : a1, e1 = a0 < a1 ? a1 : a0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kCcThreads) {
+    const int2 uv = reinterpret_cast<const int2*>(edges)[e];
+    const uint32_t lu = (uint32_t)(uv.x - v0), lv = (uint32_t)(uv.y - v0);
+    if (tags[e] == 1 && lu != lv && lu < (uint32_t)kCcBlock && lv < (uint32_t)kCcBlock && uv.x < n && uv.y < n)
+      lds_union(lp, (int32_t)lu, (int32_t)lv);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kCcBlock; i += kCcThreads) {
+    const int32_t v = v0 + i;
+    if (v >= n) break;
+    int32_t x = i, p;
+    while ((p = lp[x]) != x) x = p;       // no unions run any more: a plain walk
+    parent[v] = v0 + x;
+  }
+}
+
+// Pass two: validates every edge and hooks the collapsible ones that pass
+// one did not join (lock-free union-find on the global forest; larger root
+// below smaller, so every root stays the smallest id of its tree).
+__global__ void k_cc_cross(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
+                           int32_t* parent, int32_t n, const int64_t* __restrict__ bounds, unsigned* err) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
     const int2 uv = reinterpret_cast<const int2*>(edges)[e];
     const int32_t u = uv.x, v = uv.y;
@@ -67,75 +197,11 @@ __global__ void k_cc_link_min(const int32_t* __restrict__ edges, const uint8_t* 
       continue;
     }
     if (t == 0 || u == v) continue;
-    const int32_t lo = u < v ? u : v, hi = u < v ? v : u;
-    atomicMin(parent + hi, lo);
-  }
-}
-
-// Root-level linking round (minimum-label hooking in the manner of
-// Shiloach-Vishkin): for a collapsible edge whose ends have different
-// parents pu, pv, the larger of the two is pointed at the smaller.  Both lie
-// in the edge's component and the value only decreases, so the forest stays
-// valid; a pointer it replaces may drop a link, which the final lock-free
-// pass over every edge restores.
-// Lanes of a wave that hook the same vertex first take the minimum of their
-// targets, so each distinct vertex costs one atomic per wave (the trees of a
-// large component meet along long boundaries, whose edges sit side by side
-// in the edge list).  The loop bound is uniform per workgroup, so every lane
-// of a wave takes part in the lane exchanges.
-__global__ void k_cc_link_roots(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
-                                int32_t* parent, int32_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
-    const int64_t e = base + threadIdx.x;
-    bool want = false;
-    int32_t lo = 0, hi = 0;
-    if (e < m && tags[e] == 1) {
-      const int2 uv = reinterpret_cast<const int2*>(edges)[e];
-      const int32_t u = uv.x, v = uv.y;
-      if (u != v && u >= 0 && u < n && v >= 0 && v < n) {
-        const int32_t pu = parent[u], pv = parent[v];
-        lo = pu < pv ? pu : pv;
-        hi = pu < pv ? pv : pu;
-        want = pu != pv && parent[hi] > lo;
-      }
+    const int32_t bu = u >> kCcLog;
+    if (bu == (v >> kCcLog)) {            // joined by pass one if e lies in its block's range
+      const int64_t s0 = bounds[bu], s1 = bounds[bu + 1];
+      if (e >= (s0 < s1 ? s0 : s1) && e < (s0 < s1 ? s1 : s0)) continue;
     }
-    uint64_t pend = __ballot(want);
-    while (pend) {
-      const int leader = __ffsll((unsigned long long)pend) - 1;
-      const int32_t h = __shfl(hi, leader);
-      const bool mine = want && hi == h;
-      int32_t mn = mine ? lo : INT32_MAX;
-#pragma unroll
-      for (int d = kWave / 2; d > 0; d >>= 1) {
-        const int32_t o = __shfl_xor(mn, d);
-        mn = o < mn ? o : mn;
-      }
-      if ((int)lane_id() == leader) atomicMin(parent + h, mn);
-      pend &= ~__ballot(mine);
-      want = want && !mine;
-    }
-  }
-}
-
-// parent[v] = root of v by a read-only walk.  Entries other threads update
-// meanwhile only move to ancestors, so every walk still ends at a root.
-__global__ void k_cc_flatten(int32_t* parent, int32_t n) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    int32_t x = parent[v], p;
-    while ((p = parent[x]) != x) x = p;
-    parent[v] = x;
-  }
-}
-
-// Lock-free union of the remaining edges whose ends sit in different trees
-// (input already validated by k_cc_link_min).
-__global__ void k_cc_hook(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
-                          int32_t* parent, int32_t n) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-    const int2 uv = reinterpret_cast<const int2*>(edges)[e];
-    const int32_t u = uv.x, v = uv.y;
-    if (tags[e] != 1 || u == v || u < 0 || u >= n || v < 0 || v >= n) continue;
     int32_t ru = find_root(parent, u), rv = find_root(parent, v);
     while (ru != rv) {
       const int32_t lo = ru < rv ? ru : rv, hi = ru < rv ? rv : ru;
@@ -148,11 +214,10 @@ __global__ void k_cc_hook(const int32_t* __restrict__ edges, const uint8_t* __re
   }
 }
 
-__global__ void k_cc_compress(int32_t* parent, int32_t n, uint32_t* __restrict__ flag) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = find_root(parent, (int32_t)v);
-    flag[v] = (r == (int32_t)v) ? 1u : 0u;
-  }
+// flag[v] = 1 for the roots (parent[v] == v: the smallest id of a component)
+__global__ void k_cc_roots(const int32_t* __restrict__ parent, int32_t n, uint32_t* __restrict__ flag) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    flag[v] = (parent[v] == (int32_t)v) ? 1u : 0u;
 }
 
 __global__ void k_cc_label(const int32_t* __restrict__ parent, const uint32_t* __restrict__ rank, int32_t n,
@@ -163,11 +228,6 @@ __global__ void k_cc_label(const int32_t* __restrict__ parent, const uint32_t* _
     map[v] = (int32_t)rank[x];
   }
 }
-
-// Root-linking rounds before the lock-free pass.  On the tet grids two
-// rounds leave (almost) no edge between different trees; the lock-free pass
-// merges whatever remains, so the count only affects speed.
-constexpr int kRootRounds = 2;
 
 static unsigned gs_blocks(int64_t n) {
   int64_t b = (n + kWG - 1) / kWG;
@@ -182,20 +242,15 @@ int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edge
   if (n == 0) return 0;
   int32_t* parent = s.parent;
   uint32_t* flag = s.flag;
+  const unsigned nb = (unsigned)(((int64_t)n + kCcBlock - 1) >> kCcLog);
   k_clear_u32<<<1, 1, 0, c->stream>>>(c->d_err);
-  k_cc_init<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
+  k_cc_local<<<nb, kCcThreads, 0, c->stream>>>(edges, tags, m, n, parent, s.bounds);
   AGC_LAUNCH_CHECK();
   if (m > 0) {
-    k_cc_link_min<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n, c->d_err);
-    k_cc_flatten<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
-    for (int r = 0; r < kRootRounds; ++r) {
-      k_cc_link_roots<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n);
-      k_cc_flatten<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n);
-    }
-    k_cc_hook<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n);
+    k_cc_cross<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n, s.bounds, c->d_err);
     AGC_LAUNCH_CHECK();
   }
-  k_cc_compress<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n, flag);
+  k_cc_roots<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n, flag);
   AGC_LAUNCH_CHECK();
   scan_u32_into(c, flag, flag, n, s.scan_sums);
   k_cc_label<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, flag, n, map);
@@ -206,13 +261,25 @@ int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edge
   return (int32_t)h[0];
 }
 
-int64_t agg_scratch_words(int32_t n) { return 2 * ((int64_t)n + 64) + scan_sums_words(n) + 64; }
+// parent [n], flag [n + 1], scan sums, bounds [nb + 1] (64-bit), each from a
+// 256-byte boundary
+int64_t agg_scratch_words(int32_t n) {
+  const int64_t nb = ((int64_t)n + kCcBlock - 1) >> kCcLog;
+  return 2 * ((int64_t)n + 64) + scan_sums_words(n) + 64 + 2 * (nb + 1) + 64;
+}
+
+static int64_t round64(int64_t w) { return (w + 63) & ~(int64_t)63; }
 
 AggScratch agg_scratch_carve(uint32_t* base, int32_t n) {
   AggScratch s;
+  int64_t off = 0;
   s.parent = reinterpret_cast<int32_t*>(base);
-  s.flag = base + ((int64_t)n + 64);
-  s.scan_sums = base + 2 * ((int64_t)n + 64);
+  off = round64((int64_t)n);
+  s.flag = base + off;
+  off += round64((int64_t)n + 1);
+  s.scan_sums = base + off;
+  off += round64(scan_sums_words(n));
+  s.bounds = reinterpret_cast<int64_t*>(base + off);
   return s;
 }
 

@@ -126,6 +126,7 @@ struct AggScratch {
   int32_t* parent = nullptr;     // [n]
   uint32_t* flag = nullptr;      // [n + 1]
   uint32_t* scan_sums = nullptr; // [scan_sums_words(n)]
+  int64_t* bounds = nullptr;     // [vertex blocks + 1]: first edge of each block's range
 };
 int64_t agg_scratch_words(int32_t n);
 AggScratch agg_scratch_carve(uint32_t* base, int32_t n);

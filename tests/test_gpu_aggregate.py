@@ -74,6 +74,28 @@ def test_map_graphs(ctx, case):
     assert nc == nref and np.array_equal(m, ref)
 
 
+@pytest.mark.parametrize("order", ["shuffled", "descending"])
+def test_map_grid_edge_order(ctx, order):
+    """The 32^3 grid's edges out of the sorted order the block pass reads as
+    ranges: shuffled with half the pairs reversed, and sorted by smaller end
+    descending; the map must not change."""
+    p = problem("c4")
+    rng = np.random.default_rng(11)
+    if order == "shuffled":
+        perm = rng.permutation(p["edges"].shape[0])
+        e = p["edges"][perm].copy()
+        flip = rng.random(e.shape[0]) < 0.5
+        e[flip] = e[flip][:, ::-1]
+    else:
+        perm = np.argsort(-p["edges"].min(axis=1), kind="stable")
+        e = p["edges"][perm]
+    t = p["tags"][perm]
+    log(f"[agg] c4 edges {order}")
+    m, nc = _agg(ctx, p["n_verts"], e, t)
+    ref, nref = oagg.components(p["n_verts"], p["edges"], p["tags"])
+    assert nc == nref and np.array_equal(m, ref)
+
+
 def test_map_all_or_nothing(ctx):
     p = problem("c4")
     m, nc = _agg(ctx, p["n_verts"], p["edges"], np.zeros_like(p["tags"]))
