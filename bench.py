@@ -230,13 +230,15 @@ def cpu_baseline_slab(p, tags, rtol, layers, full):
 # ------------------------------------------------------------ c5: drifting systems
 
 def drift_systems(args, p, ctx, mesh, dev, t, torch, agc, synth, setup_ms):
-    """Ten systems on one mesh whose tags drift by about 10% from one to the next."""
+    """args.systems (ten by default) systems on one mesh whose tags drift by about 10% from one to the next;
+    the legs measured are those named in args.legs (the FP64 coarsened solve always)."""
     from concurrent.futures import ThreadPoolExecutor
     n_e, n_v = int(p["elem_verts"].shape[0]), int(p["n_verts"])
-    log(f"[bench] drifting tags of {N_DRIFT_SYSTEMS} systems")
-    with ThreadPoolExecutor(max_workers=min(N_DRIFT_SYSTEMS, 8)) as ex:
-        tag_np = list(ex.map(lambda it: synth.drift_tags(p, it), range(N_DRIFT_SYSTEMS)))
-    flips = [None] + [round(float(np.mean(tag_np[i] != tag_np[i - 1])), 4) for i in range(1, N_DRIFT_SYSTEMS)]
+    ns, legs = args.systems, args.legs
+    log(f"[bench] drifting tags of {ns} systems")
+    with ThreadPoolExecutor(max_workers=min(ns, 8)) as ex:
+        tag_np = list(ex.map(lambda it: synth.drift_tags(p, it), range(ns)))
+    flips = [None] + [round(float(np.mean(tag_np[i] != tag_np[i - 1])), 4) for i in range(1, ns)]
     edges = t(p["edges"], torch.int32)
     tags = [t(tg, torch.uint8) for tg in tag_np]
     eh, g = t(p["elem_H"], torch.float64), t(p["g"], torch.float64)
@@ -253,15 +255,16 @@ def drift_systems(args, p, ctx, mesh, dev, t, torch, agc, synth, setup_ms):
 
     # untimed float64 references (rtol 1e-12), one per system
     refs, ref_info = [], []
-    for s in range(N_DRIFT_SYSTEMS):
+    for s in range(ns):
         ref_info.append(solve(s, rtol=1e-12, max_iter=50000))
         refs.append(x.clone())
-    solve(0, rtol=1e-12, max_iter=50000, coarsen=0)
-    ref_fine = x.clone()
+    if "fine" in legs:
+        solve(0, rtol=1e-12, max_iter=50000, coarsen=0)
+        ref_fine = x.clone()
     torch.cuda.synchronize()
 
     K, W = args.steps, args.warmup
-    per = [K // N_DRIFT_SYSTEMS + (1 if s < K % N_DRIFT_SYSTEMS else 0) for s in range(N_DRIFT_SYSTEMS)]
+    per = [K // ns + (1 if s < K % ns else 0) for s in range(ns)]
 
     def timed(kw, label):
         """W warm-up solves (system 0), then K timed solves spread over the systems."""
@@ -269,10 +272,10 @@ def drift_systems(args, p, ctx, mesh, dev, t, torch, agc, synth, setup_ms):
             solve(0, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ms = [[] for _ in range(N_DRIFT_SYSTEMS)]
-        infos = [None] * N_DRIFT_SYSTEMS
+        ms = [[] for _ in range(ns)]
+        infos = [None] * ns
         last = t0
-        for s in range(N_DRIFT_SYSTEMS):
+        for s in range(ns):
             for _ in range(per[s]):
                 infos[s] = solve(s, **kw)
                 now = time.perf_counter()
@@ -289,63 +292,72 @@ def drift_systems(args, p, ctx, mesh, dev, t, torch, agc, synth, setup_ms):
     mix_kw = dict(rtol=args.rtol, precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, max_iter=50000)
     log("[bench] coarsened FP64 solves (the metric)")
     med64, mean64, ms64, info64 = timed(c64_kw, "coarsened FP64")
-    log("[bench] coarsened mixed-precision solves")
-    medmx, meanmx, msmx, infomx = timed(mix_kw, "coarsened mixed")
+    if "mixed" in legs:
+        log("[bench] coarsened mixed-precision solves")
+        medmx, meanmx, msmx, infomx = timed(mix_kw, "coarsened mixed")
 
     systems = []
-    for s in range(N_DRIFT_SYSTEMS):
+    for s in range(ns):
         i64 = solve(s, **c64_kw)
         e64 = rel(refs[s])
         ph = solve(s, timing=1, **c64_kw)
-        imx = solve(s, **mix_kw)
-        emx = rel(refs[s])
+        if "mixed" in legs:
+            imx = solve(s, **mix_kw)
+            emx = rel(refs[s])
+        else:
+            imx, emx = types.SimpleNamespace(pcg_iters=None, refine_iters=None), None
         systems.append({
             "system": s, "flip_fraction": flips[s], "n_coarse": i64.n_coarse, "nnzb_coarse": int(i64.nnzb),
             "fp64": {"ms": round(float(np.mean(ms64[s])), 3) if ms64[s] else None, "pcg_iters": i64.pcg_iters,
                      "rel_res": i64.rel_res, "rel_err": e64},
-            "mixed": {"ms": round(float(np.mean(msmx[s])), 3) if msmx[s] else None, "pcg_iters": imx.pcg_iters,
+            "mixed": {"ms": round(float(np.mean(msmx[s])), 3) if "mixed" in legs and msmx[s] else None,
+                      "pcg_iters": imx.pcg_iters,
                       "refine_iters": imx.refine_iters, "rel_err": emx},
             "fp64_phase_ms": {"aggregate": round(ph.ms_aggregate, 3), "assemble": round(ph.ms_assemble, 3),
                               "pcg": round(ph.ms_pcg, 3), "prolong": round(ph.ms_prolong, 3)},
             "assembly_gbs": round(assembly_bytes(n_e, n_v, int(ph.nnzb)) / (ph.ms_assemble * 1e-3) / 1e9, 1),
         })
         log(f"[bench] system {s}: flips {flips[s]} n_c={i64.n_coarse} nnzb={i64.nnzb} fp64 iters={i64.pcg_iters} "
-            f"err={e64:.2e}; mixed iters={imx.pcg_iters} err={emx:.2e}; phases agg {ph.ms_aggregate:.2f} "
+            f"err={e64:.2e}; mixed iters={imx.pcg_iters} err={emx}; phases agg {ph.ms_aggregate:.2f} "
             f"asm {ph.ms_assemble:.2f} pcg {ph.ms_pcg:.2f} prl {ph.ms_prolong:.2f} ms")
 
     # the dominant kernel: the fused SpMV of the FP64 coarse PCG, system 0
     ti = solve(0, timing=2, **c64_kw)
     roof = roofline("k_pcg_spmv<double> (fused SpMV w = A z and z^T w, float64 coarse matrix), system 0",
                     int(ti.nnzb), ti.n_coarse, 8, 8, ti, measured_traffic("c5", "f64"))
-    tm = solve(0, timing=2, **mix_kw)
-    roof_mx = roofline("k_pcg_spmv<float> (float32 coarse matrix, float32 z), system 0", int(tm.nnzb), tm.n_coarse,
-                       4, 4, tm, None)
     log(f"[bench] SpMV float64 coarse: {roof['avg_launch_us']:.1f} us = {roof['achieved']:.0f} GB/s "
-        f"({roof['frac']:.3f}); float32: {roof_mx['avg_launch_us']:.1f} us ({roof_mx['frac']:.3f})")
+        f"({roof['frac']:.3f})")
+    if "mixed" in legs:
+        tm = solve(0, timing=2, **mix_kw)
+        roof_mx = roofline("k_pcg_spmv<float> (float32 coarse matrix, float32 z), system 0", int(tm.nnzb),
+                           tm.n_coarse, 4, 4, tm, None)
+        log(f"[bench] SpMV float32 coarse: {roof_mx['avg_launch_us']:.1f} us ({roof_mx['frac']:.3f})")
 
-    # the fine FP64 comparator (its system does not depend on the tags)
-    log("[bench] fine FP64 solves (comparator)")
-    kf = max(2, K // 2)
-    msf, finfo = time_steps(lambda: solve(0, rtol=args.rtol_fine, coarsen=0, max_iter=50000), kf, 1, torch)
-    err_f = rel(ref_fine)
-    fi = solve(0, rtol=args.rtol_fine, coarsen=0, timing=2, max_iter=50000)
-    roof_f = roofline("k_pcg_spmv<double> on the fine matrix", int(fi.nnzb), fi.n_coarse, 8, 8, fi, None)
-    ms_fine = float(np.mean(msf))
-    log(f"[bench]   {ms_fine:.2f} ms/solve  pcg_iters={finfo.pcg_iters} err={err_f:.2e}; SpMV "
-        f"{roof_f['avg_launch_us']:.1f} us ({roof_f['frac']:.3f})")
+    if "fine" in legs:   # the fine FP64 comparator (its system does not depend on the tags)
+        log("[bench] fine FP64 solves (comparator)")
+        kf = max(2, K // 2)
+        msf, finfo = time_steps(lambda: solve(0, rtol=args.rtol_fine, coarsen=0, max_iter=50000), kf, 1, torch)
+        err_f = rel(ref_fine)
+        fi = solve(0, rtol=args.rtol_fine, coarsen=0, timing=2, max_iter=50000)
+        roof_f = roofline("k_pcg_spmv<double> on the fine matrix", int(fi.nnzb), fi.n_coarse, 8, 8, fi, None)
+        ms_fine = float(np.mean(msf))
+        log(f"[bench]   {ms_fine:.2f} ms/solve  pcg_iters={finfo.pcg_iters} err={err_f:.2e}; SpMV "
+            f"{roof_f['avg_launch_us']:.1f} us ({roof_f['frac']:.3f})")
 
     f32in = None
     if not args.no_extras:
         f32in = f32_element_input(args, p, ctx, mesh, edges, tags[0], eh, g, refs[0], args.rtol, torch, agc)
     all64 = [v for s in ms64 for v in s]
+    fl = [f for f in flips if f]
+    flip_range = f"{min(fl):.1%}-{max(fl):.1%}" if fl else "none"
     out = {
         "metric": METRIC, "value": round(med64, 4), "unit": "ms", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": round(mean64, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {
             "workload": (f"c5: cube grid 128^3, 5 tets/cube, {n_v} vertices, {n_e} tets, {p['frac']:.0%} collapsible "
-                         f"edges, {N_DRIFT_SYSTEMS} systems whose tags drift (flips {min(f for f in flips if f):.1%}-"
-                         f"{max(f for f in flips if f):.1%} per system), each re-aggregated and re-assembled; "
+                         f"edges, {ns} systems whose tags drift ({flip_range} of the tags flip per system), each "
+                         f"re-aggregated and re-assembled; "
                          f"FP64 coarsened solve to rtol {args.rtol:g}; value = median over the systems of their mean "
                          f"ms per solve, ms_per_step = mean over the {K} timed solves ({per[0]} per system)"),
             "n_verts": n_v, "n_elems": n_e, "mesh_setup_ms": round(setup_ms, 2), "rtol": args.rtol,
@@ -354,22 +366,25 @@ def drift_systems(args, p, ctx, mesh, dev, t, torch, agc, synth, setup_ms):
         "roofline": roof,
         "cpu_baseline": None,
         "solution_error": {"coarse_fp64_max": max(sy["fp64"]["rel_err"] for sy in systems),
-                           "coarse_mixed_max": max(sy["mixed"]["rel_err"] for sy in systems),
-                           "fine_fp64": err_f,
                            "against": "each system's float64 solve to rtol 1e-12 (coarsened: P A_c^-1 P^T g; "
                                       "fine: H^-1 g)"},
-        "mixed": {"value_ms": round(medmx, 4), "ms_per_step": round(meanmx, 4), "inner_rtol": args.inner_rtol,
-                  "speedup_vs_fine_fp64": round(ms_fine / medmx, 3), "roofline": roof_mx,
-                  "step_ms": spread([v for s in msmx for v in s])},
-        "fine_fp64": {"ms_per_solve": round(ms_fine, 4), "rtol": args.rtol_fine, "pcg_iters": finfo.pcg_iters,
-                      "steps": kf, "roofline": roof_f},
-        "speedup_vs_fine_fp64": round(ms_fine / med64, 3),
         "systems": systems,
     }
+    if "mixed" in legs:
+        out["solution_error"]["coarse_mixed_max"] = max(sy["mixed"]["rel_err"] for sy in systems)
+        out["mixed"] = {"value_ms": round(medmx, 4), "ms_per_step": round(meanmx, 4), "inner_rtol": args.inner_rtol,
+                        "roofline": roof_mx, "step_ms": spread([v for s in msmx for v in s])}
+    if "fine" in legs:
+        out["solution_error"]["fine_fp64"] = err_f
+        out["fine_fp64"] = {"ms_per_solve": round(ms_fine, 4), "rtol": args.rtol_fine, "pcg_iters": finfo.pcg_iters,
+                            "steps": kf, "roofline": roof_f}
+        out["speedup_vs_fine_fp64"] = round(ms_fine / med64, 3)
+        if "mixed" in legs:
+            out["mixed"]["speedup_vs_fine_fp64"] = round(ms_fine / medmx, 3)
     if f32in is not None:
         out["f32_element_input_system0"] = f32in
     refs.clear()
-    del probs, tags, eh, g, rest, edges, x, mp, ref_fine
+    del probs, tags, eh, g, rest, edges, x, mp
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: the oracle on a slab of system 0")
         full = {"nnzb": int(systems[0]["nnzb_coarse"]), "iters": int(systems[0]["fp64"]["pcg_iters"])}
@@ -623,6 +638,29 @@ def single_system(args, name, ctx, torch, agc, synth, with_extras, headline):
         "speedup_mixed_vs_fine_fp64": round(float(np.mean(msf) / np.mean(msmx)), 3),
         "n_verts": p["n_verts"], "n_elems": int(p["elem_verts"].shape[0]), "mesh_setup_ms": round(setup_ms, 2),
     }
+    if "n_contacts" in p:
+        # Contact pairs change every Newton iteration in the paper's loop, and the static plan covers
+        # the contact elements too: the plan rebuilt for each new contact set costs this much per
+        # iteration on both paths (the coarsened and the fine solve use the same plan).
+        reps = max(3, args.steps // 4)
+        plan_ms = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            m2 = agc.agc_mesh_create(ctx, p["n_verts"], ev)
+            plan_ms.append((time.perf_counter() - t1) * 1e3)
+            m2.close()
+        pm = float(np.median(plan_ms))
+        res["contact_replan"] = {
+            "plan_ms": round(pm, 3), "plan_ms_spread": spread(plan_ms),
+            "coarse_mixed_with_plan_ms": round(pm + float(np.mean(msmx)), 3),
+            "coarse_fp64_with_plan_ms": round(pm + float(np.mean(ms64)), 3),
+            "fine_fp64_with_plan_ms": round(pm + float(np.mean(msf)), 3),
+            "speedup_mixed_with_plan": round((pm + float(np.mean(msf))) / (pm + float(np.mean(msmx))), 3),
+            "note": "agc_mesh_create of the tets and the contact elements, as needed after every change of the "
+                    "contact set; added to each path's solve"}
+        log(f"[bench] {name} plan rebuild per contact change {pm:.2f} ms: mixed {pm + np.mean(msmx):.2f} ms vs fine "
+            f"{pm + np.mean(msf):.2f} ms per Newton iteration")
     if with_extras:
         res["f32_element_input"] = f32_element_input(args, p, ctx, mesh, edges, tags, eh, g, ref_coarse, rtol, torch,
                                                      agc)
@@ -666,12 +704,18 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-4, help="mixed: tolerance of each inner solve")
     ap.add_argument("--cpu-layers", type=int, default=24, help="cube layers of the CPU baseline's slab sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--systems", type=int, default=N_DRIFT_SYSTEMS, help="c5: number of drifting systems")
+    ap.add_argument("--legs", default="fp64,mixed,fine",
+                    help="c5: solves to measure, from fp64 (the metric, always), mixed, fine")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 64^3 grid's figures (post-coarsening, affine embedding, tagging, adjoint, Newton "
                          "step; with --config c1..c4 those of that system)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates the HBM counters), then exit")
     args = ap.parse_args()
+    args.legs = set(args.legs.split(",")) | {"fp64"}
+    if not args.legs <= {"fp64", "mixed", "fine"} or not 1 <= args.systems <= N_DRIFT_SYSTEMS:
+        ap.error("--legs takes fp64, mixed, fine; --systems 1..10")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: the coarsened solve runs on one GPU; run it with --gpus 1 "
