@@ -43,6 +43,21 @@ __device__ int32_t find_root(int32_t* parent, int32_t v) {
   return cur;
 }
 
+// find_root whose answer is a root at the time of the call: the walk uses
+// plain loads, but a node that looks like a root in this XCD's cache is
+// confirmed with a device-coherent load (a hook made on another XCD leaves
+// the cached line stale until it is evicted; hooking a stale root would only
+// fail its compare-and-swap, at the cost of a device-scope round trip).
+__device__ int32_t find_root_coherent(int32_t* parent, int32_t v) {
+  int32_t x = v;
+  for (;;) {
+    int32_t r = find_root(parent, x);
+    const int32_t q = __hip_atomic_load(parent + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (q == r) return r;
+    x = q;
+  }
+}
+
 __global__ void k_cc_init(int32_t* __restrict__ parent, int32_t n) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
     parent[v] = (int32_t)v;
@@ -64,10 +79,16 @@ __global__ void k_cc_init(int32_t* __restrict__ parent, int32_t n) {
 // edge, and an edge the first pass cannot join locally is joined by the
 // second.
 
-constexpr int kCcBlock = 4096;          // vertices per block (16 KB of LDS)
-constexpr int kCcLog = 12;
-static_assert((1 << kCcLog) == kCcBlock, "block size");
-constexpr int kCcThreads = 1024;        // threads of a block's workgroup
+#ifndef AGC_CC_LOG
+#define AGC_CC_LOG 12
+#endif
+constexpr int kCcLog = AGC_CC_LOG;
+constexpr int kCcBlock = 1 << kCcLog;   // vertices per block (4096: 16 KB of LDS)
+#ifndef AGC_CC_THREADS
+#define AGC_CC_THREADS 1024
+#endif
+constexpr int kCcThreads = AGC_CC_THREADS;   // threads of a block's workgroup
+constexpr int kCcBatch = 8;             // edges a thread loads at once
 
 __device__ __forceinline__ int32_t edge_key(const int32_t* edges, int64_t e) {
   const int2 uv = reinterpret_cast<const int2*>(edges)[e];
@@ -163,11 +184,25 @@ __global__ __launch_bounds__(kCcThreads) void k_cc_local(const int32_t* __restri
     if (b == nb - 1) bounds[nb] = m;
   }
   const int64_t e0 = a0 < a1 ? a0 : a1, e1 = a0 < a1 ? a1 : a0;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kCcThreads) {
-    const int2 uv = reinterpret_cast<const int2*>(edges)[e];
-    const uint32_t lu = (uint32_t)(uv.x - v0), lv = (uint32_t)(uv.y - v0);
-    if (tags[e] == 1 && lu != lv && lu < (uint32_t)kCcBlock && lv < (uint32_t)kCcBlock && uv.x < n && uv.y < n)
-      lds_union(lp, (int32_t)lu, (int32_t)lv);
+  // kCcBatch edges per thread are loaded together (indices past the range
+  // repeat its last edge and are masked), then joined
+  for (int64_t eb = e0 + threadIdx.x; eb < e1; eb += (int64_t)kCcThreads * kCcBatch) {
+    int2 uv[kCcBatch];
+    uint8_t tg[kCcBatch];
+#pragma unroll
+    for (int j = 0; j < kCcBatch; ++j) {
+      const int64_t e = eb + (int64_t)j * kCcThreads;
+      const int64_t ec = e < e1 ? e : e1 - 1;
+      uv[j] = reinterpret_cast<const int2*>(edges)[ec];
+      tg[j] = tags[ec];
+    }
+#pragma unroll
+    for (int j = 0; j < kCcBatch; ++j) {
+      const uint32_t lu = (uint32_t)(uv[j].x - v0), lv = (uint32_t)(uv[j].y - v0);
+      if (eb + (int64_t)j * kCcThreads < e1 && tg[j] == 1 && lu != lv && lu < (uint32_t)kCcBlock &&
+          lv < (uint32_t)kCcBlock && uv[j].x < n && uv[j].y < n)
+        lds_union(lp, (int32_t)lu, (int32_t)lv);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kCcBlock; i += kCcThreads) {
@@ -181,51 +216,105 @@ __global__ __launch_bounds__(kCcThreads) void k_cc_local(const int32_t* __restri
 
 // Pass two: validates every edge and hooks the collapsible ones that pass
 // one did not join (lock-free union-find on the global forest; larger root
-// below smaller, so every root stays the smallest id of its tree).
-__global__ void k_cc_cross(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags, int64_t m,
-                           int32_t* parent, int32_t n, const int64_t* __restrict__ bounds, unsigned* err) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-    const int2 uv = reinterpret_cast<const int2*>(edges)[e];
-    const int32_t u = uv.x, v = uv.y;
-    const uint8_t t = tags[e];
-    if (u < 0 || u >= n || v < 0 || v >= n) {
-      atomicOr(err, kErrRange);
-      continue;
+// below smaller, so every root stays the smallest id of its tree).  The ends
+// of such an edge lie in two blocks, so their parents (the local roots of
+// pass one) differ, and along a block boundary long runs of edges join the
+// same two local trees.  Each workgroup takes a contiguous range of edges;
+// the lanes of a wave with the same pair of parents leave the union to one
+// of them, and a workgroup remembers in LDS the pairs it has joined (a pair
+// joined once stays joined; a stale or overwritten entry only repeats a
+// union, which changes nothing).  Loop bounds are uniform per workgroup, so
+// all lanes of a wave take part in the ballots.
+constexpr int kCrossCache = 512;   // remembered pairs per workgroup (direct-mapped)
+
+__global__ __launch_bounds__(kWG) void k_cc_cross(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags,
+                                                  int64_t m, int32_t* parent, int32_t n,
+                                                  const int64_t* __restrict__ bounds, unsigned* err) {
+  __shared__ uint64_t seen[kCrossCache];
+  for (int i = threadIdx.x; i < kCrossCache; i += kWG) seen[i] = ~0ull;
+  __syncthreads();
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t e_lo = (int64_t)blockIdx.x * per, e_hi = e_lo + per < m ? e_lo + per : m;
+  const unsigned lane = lane_id();
+  for (int64_t base = e_lo; base < e_hi; base += kWG) {
+    const int64_t e = base + threadIdx.x;
+    bool want = false;
+    int32_t lo = 0, hi = 0;
+    if (e < e_hi) {
+      const int2 uv = reinterpret_cast<const int2*>(edges)[e];
+      const int32_t u = uv.x, v = uv.y;
+      const uint8_t t = tags[e];
+      if (u < 0 || u >= n || v < 0 || v >= n) {
+        atomicOr(err, kErrRange);
+      } else if (t > 1) {
+        atomicOr(err, kErrTag);
+      } else if (t == 1 && u != v) {
+        want = true;
+        const int32_t bu = u >> kCcLog;
+        if (bu == (v >> kCcLog)) {            // joined by pass one if e lies in its block's range
+          const int64_t s0 = bounds[bu], s1 = bounds[bu + 1];
+          want = !(e >= (s0 < s1 ? s0 : s1) && e < (s0 < s1 ? s1 : s0));
+        }
+        if (want) {   // the ends' parents: their local roots from pass one, or ancestors of them
+          const int32_t pu = ld_parent(parent, u), pv = ld_parent(parent, v);
+          lo = pu < pv ? pu : pv;
+          hi = pu < pv ? pv : pu;
+          want = pu != pv;
+        }
+      }
     }
-    if (t > 1) {
-      atomicOr(err, kErrTag);
-      continue;
-    }
-    if (t == 0 || u == v) continue;
-    const int32_t bu = u >> kCcLog;
-    if (bu == (v >> kCcLog)) {            // joined by pass one if e lies in its block's range
-      const int64_t s0 = bounds[bu], s1 = bounds[bu + 1];
-      if (e >= (s0 < s1 ? s0 : s1) && e < (s0 < s1 ? s1 : s0)) continue;
-    }
-    int32_t ru = find_root(parent, u), rv = find_root(parent, v);
-    while (ru != rv) {
-      const int32_t lo = ru < rv ? ru : rv, hi = ru < rv ? rv : ru;
-      const int32_t old = atomicCAS(parent + hi, hi, lo);
-      if (old == hi) break;                       // hooked hi below lo
-      // hi stopped being a root meanwhile: continue from its new root
-      const int32_t r = find_root(parent, old);
-      if (ru == hi) ru = r; else rv = r;
+    uint64_t pend = __ballot(want);
+    while (pend) {
+      const int leader = __ffsll((unsigned long long)pend) - 1;
+      const int32_t h = __shfl(hi, leader), l = __shfl(lo, leader);
+      pend &= ~__ballot(want && hi == h && lo == l);
+      if ((int)lane == leader) {
+        const uint64_t key = ((uint64_t)(uint32_t)h << 32) | (uint32_t)l;
+        const uint32_t slot = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 55) & (kCrossCache - 1);
+        if (seen[slot] != key) {
+          int32_t ru = find_root_coherent(parent, l), rv = find_root_coherent(parent, h);
+          while (ru != rv) {
+            const int32_t a = ru < rv ? ru : rv, b = ru < rv ? rv : ru;
+            const int32_t old = atomicCAS(parent + b, b, a);
+            if (old == b) break;                    // hooked b below a
+            // b stopped being a root meanwhile: continue from its new root
+            const int32_t r = find_root_coherent(parent, old);
+            if (ru == b) ru = r; else rv = r;
+          }
+          seen[slot] = key;
+        }
+      }
     }
   }
 }
 
-// flag[v] = 1 for the roots (parent[v] == v: the smallest id of a component)
-__global__ void k_cc_roots(const int32_t* __restrict__ parent, int32_t n, uint32_t* __restrict__ flag) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    flag[v] = (parent[v] == (int32_t)v) ? 1u : 0u;
+// Root bits: word w holds, in bit i, whether vertex 64 w + i is a root
+// (parent[v] == v: the smallest id of a component), one wave per word;
+// cnt[w] = its popcount.
+__global__ void k_cc_rootbits(const int32_t* __restrict__ parent, int32_t n, uint64_t* __restrict__ bits,
+                              uint32_t* __restrict__ cnt) {
+  const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nw * kWave; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = base + threadIdx.x;
+    const uint64_t word = __ballot(v < n && parent[v] == (int32_t)v);
+    if (lane_id() == 0) {
+      const int64_t w = v / kWave;
+      bits[w] = word;
+      cnt[w] = (uint32_t)__popcll(word);
+    }
+  }
 }
 
-__global__ void k_cc_label(const int32_t* __restrict__ parent, const uint32_t* __restrict__ rank, int32_t n,
-                           int32_t* __restrict__ map) {
+// map[v] = number of roots below v's root r: the roots of the words before
+// r's (rank, an exclusive scan of cnt) plus those below r in its word.
+__global__ void k_cc_label(const int32_t* __restrict__ parent, const uint64_t* __restrict__ bits,
+                           const uint32_t* __restrict__ rank, int32_t n, int32_t* __restrict__ map) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     int32_t x = (int32_t)v, p;
     while ((p = parent[x]) != x) x = p;       // read-only walk to the root
-    map[v] = (int32_t)rank[x];
+    const int32_t w = x >> 6;
+    const uint64_t below = (x & 63) ? (bits[w] << (64 - (x & 63))) : 0ull;   // bits of the word under x
+    map[v] = (int32_t)(rank[w] + (uint32_t)__popcll(below));
   }
 }
 
@@ -241,44 +330,52 @@ int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edge
                        const AggScratch& s) {
   if (n == 0) return 0;
   int32_t* parent = s.parent;
-  uint32_t* flag = s.flag;
   const unsigned nb = (unsigned)(((int64_t)n + kCcBlock - 1) >> kCcLog);
   k_clear_u32<<<1, 1, 0, c->stream>>>(c->d_err);
   k_cc_local<<<nb, kCcThreads, 0, c->stream>>>(edges, tags, m, n, parent, s.bounds);
   AGC_LAUNCH_CHECK();
   if (m > 0) {
-    k_cc_cross<<<gs_blocks(m), kWG, 0, c->stream>>>(edges, tags, m, parent, n, s.bounds, c->d_err);
+    // contiguous ranges of at least 2048 edges, up to eight workgroups per CU
+    int64_t g = (m + 2047) / 2048;
+    if (g > 2048) g = 2048;
+    k_cc_cross<<<(unsigned)g, kWG, 0, c->stream>>>(edges, tags, m, parent, n, s.bounds, c->d_err);
     AGC_LAUNCH_CHECK();
   }
-  k_cc_roots<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, n, flag);
+  const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
+  k_cc_rootbits<<<gs_blocks(nw * kWave), kWG, 0, c->stream>>>(parent, n, s.bits, s.rank);
   AGC_LAUNCH_CHECK();
-  scan_u32_into(c, flag, flag, n, s.scan_sums);
-  k_cc_label<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, flag, n, map);
+  scan_u32_into(c, s.rank, s.rank, nw, s.scan_sums);
+  k_cc_label<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, s.bits, s.rank, n, map);
   AGC_LAUNCH_CHECK();
   uint32_t* h = (uint32_t*)c->h_pcg;   // pinned scratch of the context; no PCG is in flight here
-  AGC_HIP(hipMemcpyAsync(h, flag + n, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  AGC_HIP(hipMemcpyAsync(h, s.rank + nw, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   err_throw(err_fetch(c));   // synchronises
   return (int32_t)h[0];
 }
 
-// parent [n], flag [n + 1], scan sums, bounds [nb + 1] (64-bit), each from a
-// 256-byte boundary
-int64_t agg_scratch_words(int32_t n) {
-  const int64_t nb = ((int64_t)n + kCcBlock - 1) >> kCcLog;
-  return 2 * ((int64_t)n + 64) + scan_sums_words(n) + 64 + 2 * (nb + 1) + 64;
-}
-
+// parent [n], root bits [nw] (64-bit), word ranks [nw + 1], scan sums,
+// bounds [nb + 1] (64-bit), each from a 256-byte boundary; nw = words of 64
+// vertices, nb = vertex blocks
 static int64_t round64(int64_t w) { return (w + 63) & ~(int64_t)63; }
 
+int64_t agg_scratch_words(int32_t n) {
+  const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
+  const int64_t nb = ((int64_t)n + kCcBlock - 1) >> kCcLog;
+  return round64(n) + round64(2 * nw) + round64(nw + 1) + round64(scan_sums_words(nw)) + round64(2 * (nb + 1));
+}
+
 AggScratch agg_scratch_carve(uint32_t* base, int32_t n) {
+  const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
   AggScratch s;
   int64_t off = 0;
   s.parent = reinterpret_cast<int32_t*>(base);
   off = round64((int64_t)n);
-  s.flag = base + off;
-  off += round64((int64_t)n + 1);
+  s.bits = reinterpret_cast<uint64_t*>(base + off);
+  off += round64(2 * nw);
+  s.rank = base + off;
+  off += round64(nw + 1);
   s.scan_sums = base + off;
-  off += round64(scan_sums_words(n));
+  off += round64(scan_sums_words(nw));
   s.bounds = reinterpret_cast<int64_t*>(base + off);
   return s;
 }

@@ -108,34 +108,26 @@ struct SolveResult {
   bool converged = true;   // false: max_iter (or max_refine) ended the solve; x_c is its last iterate
 };
 
-// rhs_fine: the fine vector whose restriction is the right-hand side (g, or w for the adjoint);
-// upper_async: the fine upper blocks are being gathered on the second stream (upper_async)
-SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_opts* o, const Restrictor& R,
-                         const double* rhs_fine, double* x_c, Timer* tm, bool upper_async = false) {
-  const agc::Mesh& mesh = p->mesh->m;
-  const int64_t n3c = 3 * (int64_t)R.blocks();
+// Iterations on the assembled coarse system in the context (solve_a64, and
+// solve_a for the mixed path) with right-hand side b_c (workspace
+// "solve.b"), from x_c = 0 (warm = false) or from the x_c given (warm =
+// true), until the float64 relative residual is <= rtol or max_iter PCG
+// iterations have run.  Leaves r_c = b_c - A_c x_c (float64) in the
+// workspace ("solve.rc").
+SolveResult coarse_iterate(agc_context* c, const agc_solve_opts* o, int64_t n3c, double* x_c, double rtol,
+                           int32_t max_iter, bool warm) {
   SolveResult res;
-  double* b_c = c->ws.get<double>("solve.b", n3c);
-  R.apply(rhs_fine, b_c);
-  // Both precisions assemble P^T H P once in float64 (the reduction sums in
-  // float64); the mixed path also keeps the float32 rounding of the values
-  // for its inner PCG.  The float64 matrix gives the float64 residuals.
   const bool mixed = o->precision == AGC_PREC_MIXED;
   agc::Matrix& A64 = c->solve_a64;
-  agc::Matrix* A32 = mixed ? &c->solve_a : nullptr;
-  if (upper_async) agc::upper_join(c);
-  if (R.am) agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32, upper_async);
-  else if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, R.n_c, AGC_F64, A64, A32, upper_async);
-  else agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, A64, A32);
   res.nnzb = A64.nnzb;
-  if (tm) tm->mark();
+  double* b_c = c->ws.get<double>("solve.b", n3c);
   double* y = c->ws.get<double>("solve.y", n3c);
   double* r_c = c->ws.get<double>("solve.rc", n3c);
   double bn = 0.0, rn = 0.0;
   if (!mixed) {
     int32_t it = 0;
     double rel = 0.0;
-    const int st = agc::pcg(c, A64, b_c, x_c, o->rtol, o->max_iter, &it, &rel, true);
+    const int st = agc::pcg(c, A64, b_c, x_c, rtol, max_iter, &it, &rel, !warm);
     if (st == AGC_ERR_NOT_CONVERGED) res.converged = false;
     else check_status(st, "coarse PCG");
     res.iters = it;
@@ -147,22 +139,30 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   }
   // mixed: iterative refinement x_c += A32^{-1} (b_c - A64 x_c), the inner
   // solves on the float32 values with float64 vectors and inner products
+  agc::Matrix& A32 = c->solve_a;
   double* e_c = c->ws.get<double>("solve.ec", n3c);
   double rel = 1.0;
   int32_t used = 0;
-  for (int k = 0;; ++k) {
-    if (rel <= o->rtol) break;
-    if (k >= o->max_refine || used >= o->max_iter) {   // x_c keeps the last refined iterate
+  int k0 = 0;
+  if (warm) {   // refinement from the given iterate: its float64 residual first
+    agc::spmv(c, A64, x_c, y);
+    agc::residual_norms(c, b_c, y, r_c, n3c, &bn, &rn);
+    rel = bn > 0 ? rn / bn : 0.0;
+    k0 = 1;
+  }
+  for (int k = k0;; ++k) {
+    if (rel <= rtol || (warm && bn == 0.0)) break;
+    if (k - k0 >= o->max_refine || used >= max_iter) {   // x_c keeps the last refined iterate
       res.converged = false;
       break;
     }
     int32_t it = 0;
     double irel = 0.0;
     // the inner tolerance is relative to ||r_c||; never ask for more than rtol needs
-    const double want = o->rtol / rel;
+    const double want = rtol / rel;
     const double itol = want > o->inner_rtol ? want : o->inner_rtol;
-    const int st = agc::pcg(c, *A32, k == 0 ? b_c : r_c, k == 0 ? x_c : e_c, itol, o->max_iter - used, &it,
-                            &irel, true);
+    const int st = agc::pcg(c, A32, k == 0 ? b_c : r_c, k == 0 ? x_c : e_c, itol, max_iter - used, &it, &irel,
+                            true);
     used += it;
     if (st != AGC_OK && st != AGC_ERR_NOT_CONVERGED) check_status(st, "inner PCG");
     if (k > 0) agc::axpy_vec(c, x_c, e_c, 1.0, n3c);
@@ -175,6 +175,26 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   res.iters = used;
   res.rel = bn > 0 ? rel : 0.0;
   return res;
+}
+
+// rhs_fine: the fine vector whose restriction is the right-hand side (g, or w for the adjoint)
+SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_opts* o, const Restrictor& R,
+                         const double* rhs_fine, double* x_c, Timer* tm) {
+  const agc::Mesh& mesh = p->mesh->m;
+  const int64_t n3c = 3 * (int64_t)R.blocks();
+  double* b_c = c->ws.get<double>("solve.b", n3c);
+  R.apply(rhs_fine, b_c);
+  // Both precisions assemble P^T H P once in float64 (the reduction sums in
+  // float64); the mixed path also keeps the float32 rounding of the values
+  // for its inner PCG.  The float64 matrix gives the float64 residuals.
+  const bool mixed = o->precision == AGC_PREC_MIXED;
+  agc::Matrix& A64 = c->solve_a64;
+  agc::Matrix* A32 = mixed ? &c->solve_a : nullptr;
+  if (R.am) agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32);
+  else if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, R.n_c, AGC_F64, A64, A32);
+  else agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, A64, A32);
+  if (tm) tm->mark();
+  return coarse_iterate(c, o, n3c, x_c, o->rtol, o->max_iter, false);
 }
 
 }  // namespace
@@ -243,12 +263,6 @@ agc_status agc_destroy(agc_context* c) {
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
-  if (c->aux) {
-    (void)hipStreamSynchronize(c->aux);
-    (void)hipStreamDestroy(c->aux);
-    (void)hipEventDestroy(c->fork);
-    (void)hipEventDestroy(c->join);
-  }
   delete c;
   return AGC_OK;
 }
@@ -516,19 +530,7 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   tm.mark();                                                   // 0
   Restrictor R{c, n, n, nullptr, nullptr, nullptr};
   int32_t* map = nullptr;
-  // The gather of the fine upper blocks needs no map: it runs on the second
-  // stream while the aggregation runs on the first.  The guard makes the
-  // context's stream wait for it on every way out of this call.
-  struct UpperGuard {
-    agc_context* c;
-    bool on = false;
-    ~UpperGuard() {
-      if (on && c->aux) (void)hipStreamWaitEvent(c->stream, c->join, 0);
-    }
-  } upper_guard{c};
   if (o->coarsen) {
-    agc::upper_async(c, mesh, p->elem_H);
-    upper_guard.on = true;
     map = map_out ? map_out : c->ws.get<int32_t>("solve.map", n);
     R.n_c = agc::aggregate(c, n, p->n_edges, p->edges, p->tags, map);
     R.map = map;
@@ -548,7 +550,7 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   }
   tm.mark();                                                   // 1
   double* x_c = R.map ? c->ws.get<double>("solve.xc", 3 * (int64_t)R.blocks()) : x;
-  SolveResult res = coarse_solve(c, p, o, R, p->g, x_c, &tm, upper_guard.on);  // marks 2 after assembly
+  SolveResult res = coarse_solve(c, p, o, R, p->g, x_c, &tm);  // marks 2 after assembly
   tm.mark();                                                   // 3
   if (R.map) {
     agc::err_reset(c);

@@ -463,83 +463,15 @@ __device__ __forceinline__ void fine_gather_one(const In* __restrict__ eh, const
   for (int s = 0; s < 3; ++s) F[(int64_t)(3 * r + s) * nf + f] = acc[s];
 }
 
-// The gather by runs of rows (described by wg_info): the workgroup copies
-// the pieces of a run's rows into LDS, whole and with 16-byte loads,
-// together with its plan entries (pentry) and block offsets, then forms the
-// sums of its blocks from LDS exactly as fine_gather_one does (same entries,
-// same order, so the same bits).  A run of one row with more than
-// kGatherPieces pieces reads from global memory.  Grid-stride over the runs,
-// software-pipelined: while a run's blocks are summed from LDS, the loads of
-// the next run's pieces are in flight (their sources, one run further ahead),
-// so every workgroup keeps a run's worth of loads outstanding throughout.
-// staged = 0 (element blocks not 16-byte aligned): every run reads from
-// global memory.
-template <class In>
-struct GatherStage {
-  static constexpr int kPieceVals = 36;
-  static constexpr int kChunks = kPieceVals * (int)sizeof(In) / 16;   // 16-byte chunks per piece
-  static constexpr int kFill = (kGatherPieces * kChunks + kWG - 1) / kWG;
-  static constexpr int kE = (kGatherEntries + kWG - 1) / kWG;
-  static constexpr int kB = (kGatherEntries + 1 + kWG - 1) / kWG;
-};
-
-// 16 bytes as a native vector (kept in registers across the pipelined loop)
-typedef uint32_t gvu4 __attribute__((ext_vector_type(4)));
-
-struct RunInfo {
-  uint32_t p0, np, f0, f1, k0, k1;
-  bool valid;
-};
-
-__device__ __forceinline__ RunInfo run_info(const uint4* __restrict__ wg_info, int64_t i, int64_t n_wg) {
-  RunInfo r{0, 0, 0, 0, 0, 0, false};
-  if (i < n_wg) {
-    const int64_t g = xcd_slot(i, n_wg);
-    const uint4 wa = wg_info[2 * g], wb = wg_info[2 * g + 1];
-    r = RunInfo{wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, true};
-  }
-  return r;
-}
-
-__device__ __forceinline__ bool run_staged(const RunInfo& r, int staged) {
-  return r.valid && staged && r.np != 0 && r.np <= (uint32_t)kGatherPieces;
-}
-
-// Clamped indices: a lane past the end repeats the last chunk / entry /
-// offset, so no load or store is conditional within a staged run.
-template <class In>
-__device__ __forceinline__ void gather_load_srcs(const RunInfo& r, int staged, const uint32_t* __restrict__ piece_src,
-                                                 uint32_t (&srcs)[GatherStage<In>::kFill]) {
-  using S = GatherStage<In>;
-  if (!run_staged(r, staged)) return;
-  const uint32_t nc = r.np * S::kChunks;
-#pragma unroll
-  for (int u = 0; u < S::kFill; ++u) srcs[u] = piece_src[r.p0 + min(threadIdx.x + u * kWG, nc - 1) / S::kChunks];
-}
-
-template <class In>
-__device__ __forceinline__ void gather_load_run(const RunInfo& r, int staged, const In* __restrict__ eh,
-                                                const uint32_t* __restrict__ pptr,
-                                                const uint16_t* __restrict__ pentry,
-                                                const uint32_t (&srcs)[GatherStage<In>::kFill],
-                                                gvu4 (&buf)[GatherStage<In>::kFill],
-                                                uint16_t (&ev)[GatherStage<In>::kE],
-                                                uint32_t (&bv)[GatherStage<In>::kB]) {
-  using S = GatherStage<In>;
-  if (!run_staged(r, staged)) return;
-  const uint32_t nc = r.np * S::kChunks, ne = r.k1 - r.k0, nb = r.f1 - r.f0;
-#pragma unroll
-  for (int u = 0; u < S::kE; ++u) ev[u] = pentry[r.k0 + min(threadIdx.x + u * kWG, ne - 1)];
-#pragma unroll
-  for (int u = 0; u < S::kB; ++u) bv[u] = pptr[r.f0 + min(threadIdx.x + u * kWG, nb)];
-#pragma unroll
-  for (int u = 0; u < S::kFill; ++u) {
-    const uint32_t cidx = min(threadIdx.x + u * kWG, nc - 1);
-    const uint32_t q = cidx - (cidx / S::kChunks) * S::kChunks;
-    buf[u] = reinterpret_cast<const gvu4*>(eh + (int64_t)(srcs[u] >> 2) * 144 + S::kPieceVals * (srcs[u] & 3))[q];
-  }
-}
-
+// The gather by runs of rows (one run per workgroup, described by wg_info):
+// the workgroup copies the pieces of its rows into LDS, whole and with
+// 16-byte loads, together with its plan entries (pentry) and block offsets,
+// then forms the sums of its blocks from LDS exactly as fine_gather_one does
+// (same entries, same order, so the same bits).  A run of one row with more
+// than kGatherPieces pieces reads from global memory.  Grid-stride over the
+// runs: one pass with the full grid, or a capped grid when it runs beside
+// other work.  staged = 0 (element blocks not 16-byte aligned): every run
+// reads from global memory.
 template <class In, class Acc>
 __global__ __launch_bounds__(kWG) void k_fine_gather(const In* __restrict__ eh, const uint32_t* __restrict__ pptr,
                                                      const uint32_t* __restrict__ plan,
@@ -547,65 +479,72 @@ __global__ __launch_bounds__(kWG) void k_fine_gather(const In* __restrict__ eh, 
                                                      const uint32_t* __restrict__ piece_src,
                                                      const uint4* __restrict__ wg_info, int64_t n_wg, int64_t nf,
                                                      Acc* __restrict__ F, int staged) {
-  using S = GatherStage<In>;
-  constexpr int kPieceVals = S::kPieceVals, kChunks = S::kChunks, kFill = S::kFill, kE = S::kE, kB = S::kB;
+  constexpr int kPieceVals = 36;
+  constexpr int kChunks = kPieceVals * (int)sizeof(In) / 16;   // 16-byte chunks per piece
+  constexpr int kFill = (kGatherPieces * kChunks + kWG - 1) / kWG;
   __shared__ __align__(16) In lds[kGatherPieces * kPieceVals];
   __shared__ uint16_t le[kGatherEntries];       // plan entries of the run, from k0
   __shared__ uint16_t lp[kGatherEntries + 1];   // plan offsets of its blocks, from f0
-  const int64_t step = gridDim.x;
-  int64_t i = blockIdx.x;
-  RunInfo cur = run_info(wg_info, i, n_wg), nxt = run_info(wg_info, i + step, n_wg);
-  uint32_t srcs[kFill], srcs_n[kFill];
-  gvu4 buf[kFill];
-  uint16_t ev[kE];
-  uint32_t bv[kB];
-  gather_load_srcs<In>(cur, staged, piece_src, srcs);
-  gather_load_run<In>(cur, staged, eh, pptr, pentry, srcs, buf, ev, bv);
-  gather_load_srcs<In>(nxt, staged, piece_src, srcs_n);
-  for (; i < n_wg; i += step) {
-    if (run_staged(cur, staged)) {   // uniform: write the run's loads to LDS
-      const uint32_t nc = cur.np * kChunks, ne = cur.k1 - cur.k0, nb = cur.f1 - cur.f0;
-#pragma unroll
-      for (int u = 0; u < kE; ++u) le[min(threadIdx.x + u * kWG, ne - 1)] = ev[u];
-#pragma unroll
-      for (int u = 0; u < kB; ++u) lp[min(threadIdx.x + u * kWG, nb)] = (uint16_t)(bv[u] - cur.k0);
-#pragma unroll
-      for (int u = 0; u < kFill; ++u) reinterpret_cast<gvu4*>(lds)[min(threadIdx.x + u * kWG, nc - 1)] = buf[u];
-    }
-    __syncthreads();
-    // the next run's pieces (their sources were loaded one run ago) and the
-    // sources of the run after it, issued before the sums below
-    const RunInfo nn = run_info(wg_info, i + 2 * step, n_wg);
-    uint32_t srcs_nn[kFill];
-    gather_load_run<In>(nxt, staged, eh, pptr, pentry, srcs_n, buf, ev, bv);
-    gather_load_srcs<In>(nn, staged, piece_src, srcs_nn);
-    __builtin_amdgcn_sched_barrier(0);
-    if (run_staged(cur, staged)) {
-      const uint32_t nb = cur.f1 - cur.f0;
-      for (uint32_t t = threadIdx.x; t < 3 * nb; t += kWG) {
-        const uint32_t fl = t / 3;
-        const int r = (int)(t - 3 * fl);
-        Acc acc[3] = {(Acc)0, (Acc)0, (Acc)0};
-        const uint32_t e1 = lp[fl + 1];
-        for (uint32_t e = lp[fl]; e < e1; ++e) {
-          const uint32_t pe = le[e];
-          const In* pv = lds + (pe >> 2) * kPieceVals + 12 * r + 3 * (pe & 3u);
-#pragma unroll
-          for (int sx = 0; sx < 3; ++sx) acc[sx] += (Acc)pv[sx];
-        }
-        const int64_t f = (int64_t)cur.f0 + fl;
-#pragma unroll
-        for (int sx = 0; sx < 3; ++sx) F[(int64_t)(3 * r + sx) * nf + f] = acc[sx];
-      }
-    } else if (cur.valid && cur.np != 0) {   // a row too large for LDS (or unaligned blocks): global memory
-      for (int64_t t = 3 * (int64_t)cur.f0 + threadIdx.x; t < 3 * (int64_t)cur.f1; t += kWG)
+  for (int64_t g = blockIdx.x; g < n_wg; g += gridDim.x) {
+    const uint4 wa = wg_info[2 * g], wb = wg_info[2 * g + 1];
+    const uint32_t p0 = wa.x, np = wa.y, f0 = wa.z, f1 = wa.w, k0 = wb.x, k1 = wb.y;
+    if (!staged || np > (uint32_t)kGatherPieces) {   // the same for the whole workgroup
+      for (int64_t t = 3 * (int64_t)f0 + threadIdx.x; t < 3 * (int64_t)f1; t += kWG)
         fine_gather_one<In, Acc>(eh, pptr, plan, nf, F, t);
+      continue;
+    }
+    if (np == 0) continue;   // rows without elements: no blocks
+    const uint32_t nc = np * kChunks, ne = k1 - k0, nb = f1 - f0;
+    // Branch-free loads (indices past the end repeat the last one), all
+    // issued before the first store: the piece sources, then the pieces,
+    // the entries and the block offsets.
+    constexpr int kE = (kGatherEntries + kWG - 1) / kWG, kB = (kGatherEntries + 1 + kWG - 1) / kWG;
+    uint32_t srcs[kFill];
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const uint32_t cidx = min(threadIdx.x + u * kWG, nc - 1);
+      srcs[u] = piece_src[p0 + cidx / kChunks];
+    }
+    uint16_t ev[kE];
+    uint32_t bv[kB];
+#pragma unroll
+    for (int u = 0; u < kE; ++u) ev[u] = pentry[k0 + min(threadIdx.x + u * kWG, ne - 1)];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) bv[u] = pptr[f0 + min(threadIdx.x + u * kWG, nb)];
+    uint4 buf[kFill];
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const uint32_t cidx = min(threadIdx.x + u * kWG, nc - 1);
+      const uint32_t q = cidx - (cidx / kChunks) * kChunks;
+      buf[u] = reinterpret_cast<const uint4*>(eh + (int64_t)(srcs[u] >> 2) * 144 + kPieceVals * (srcs[u] & 3))[q];
+    }
+    // the stores use the same clamped indices (a repeated index stores the
+    // value its owner stores), so no store is conditional and the loads
+    // above stay in flight together
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kE; ++u) le[min(threadIdx.x + u * kWG, ne - 1)] = ev[u];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) lp[min(threadIdx.x + u * kWG, nb)] = (uint16_t)(bv[u] - k0);
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) reinterpret_cast<uint4*>(lds)[min(threadIdx.x + u * kWG, nc - 1)] = buf[u];
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < 3 * nb; t += kWG) {
+      const uint32_t fl = t / 3;
+      const int r = (int)(t - 3 * fl);
+      Acc acc[3] = {(Acc)0, (Acc)0, (Acc)0};
+      const uint32_t e1 = lp[fl + 1];
+      for (uint32_t e = lp[fl]; e < e1; ++e) {
+        const uint32_t pe = le[e];
+        const In* pv = lds + (pe >> 2) * kPieceVals + 12 * r + 3 * (pe & 3u);
+#pragma unroll
+        for (int sx = 0; sx < 3; ++sx) acc[sx] += (Acc)pv[sx];
+      }
+      const int64_t f = (int64_t)f0 + fl;
+#pragma unroll
+      for (int sx = 0; sx < 3; ++sx) F[(int64_t)(3 * r + sx) * nf + f] = acc[sx];
     }
     __syncthreads();   // the next run refills the shared arrays
-    cur = nxt;
-    nxt = nn;
-#pragma unroll
-    for (int u = 0; u < kFill; ++u) srcs_n[u] = srcs_nn[u];
   }
 }
 
@@ -648,10 +587,6 @@ static float* companion32(const Matrix& a, Matrix* out32) {
 
 template <class In, class Acc>
 static void launch_gather(agc_context* c, const Mesh& m, const In* eh, Acc* F, hipStream_t st, unsigned grid) {
-  // k_fine_gather's XCD order needs a grid of n_wg or a multiple of kXcds
-  if ((int64_t)grid >= m.n_wg) grid = (unsigned)m.n_wg;
-  else grid -= grid % kXcds;
-  if (grid == 0) grid = 1;
   // the pieces are copied with 16-byte loads
   const int staged = ((uintptr_t)eh & 15u) == 0 ? 1 : 0;
   k_fine_gather<In, Acc><<<grid, kWG, 0, st>>>(
@@ -660,14 +595,9 @@ static void launch_gather(agc_context* c, const Mesh& m, const In* eh, Acc* F, h
   AGC_LAUNCH_CHECK();
 }
 
-constexpr unsigned kCus = 256;
-// a persistent grid: as many workgroups as fit on the chip at once (five per
-// CU by LDS), each taking every gridDim-th run with the next one in flight
-constexpr unsigned kGatherPerCu = 5;
-
 template <class In, class Acc>
 static void gather_fine(agc_context* c, const Mesh& m, const void* eh, Acc* F) {
-  launch_gather<In, Acc>(c, m, (const In*)eh, F, c->stream, kGatherPerCu * kCus);
+  launch_gather<In, Acc>(c, m, (const In*)eh, F, c->stream, (unsigned)m.n_wg);
 }
 
 template <class Acc>
@@ -680,31 +610,6 @@ static Acc* fine_upper(agc_context* c, const Mesh& m, const void* eh, int32_t h_
 
 // the float64 fine upper blocks left in the workspace by an earlier gather
 static double* upper_ready(agc_context* c, const Mesh& m) { return c->ws.get<double>("asm.F64", 9 * m.nf); }
-
-#ifndef AGC_ASYNC_GATHER_PER_CU
-#define AGC_ASYNC_GATHER_PER_CU 4
-#endif
-constexpr unsigned kAsyncGatherPerCu = AGC_ASYNC_GATHER_PER_CU;
-
-void upper_async(agc_context* c, const Mesh& m, const double* elem_h) {
-  if (!c->aux) {
-    AGC_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-    AGC_HIP(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
-    AGC_HIP(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
-  }
-  double* F = upper_ready(c, m);
-  AGC_HIP(hipEventRecord(c->fork, c->stream));
-  AGC_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
-  // a capped grid (kAsyncGatherPerCu workgroups per CU) leaves CUs to the aggregation beside it
-  const unsigned full = (unsigned)m.n_wg;
-  const unsigned grid = full < kAsyncGatherPerCu * kCus ? full : kAsyncGatherPerCu * kCus;
-  launch_gather<double, double>(c, m, elem_h, F, c->aux, grid);
-  AGC_HIP(hipEventRecord(c->join, c->aux));
-}
-
-void upper_join(agc_context* c) {
-  if (c->aux) AGC_HIP(hipStreamWaitEvent(c->stream, c->join, 0));
-}
 
 // The fine matrix borrows the mesh's static pattern (no copy per assembly).
 void assemble_fine(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, int32_t out_dtype,

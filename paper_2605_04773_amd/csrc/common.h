@@ -158,14 +158,6 @@ __device__ __forceinline__ int64_t xcd_block() {
 #endif
 }
 
-// The same renumbering for slot s of S taken by a grid-stride loop whose
-// grid is S itself or a multiple of kXcds (slot s then runs on XCD s % 8).
-__device__ __forceinline__ int64_t xcd_slot(int64_t s, int64_t S) {
-  const int64_t x = s % kXcds, i = s / kXcds;
-  const int64_t q = S / kXcds, rem = S % kXcds;
-  return x * q + (x < rem ? x : rem) + i;
-}
-
 __device__ __forceinline__ uint64_t lanemask_lt() {
   return (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
 }

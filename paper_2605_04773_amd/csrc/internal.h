@@ -124,8 +124,9 @@ void scan_u32_into(agc_context* c, const uint32_t* in, uint32_t* out, int64_t n,
 // 32-bit words by agg_scratch_carve (256-byte aligned base).
 struct AggScratch {
   int32_t* parent = nullptr;     // [n]
-  uint32_t* flag = nullptr;      // [n + 1]
-  uint32_t* scan_sums = nullptr; // [scan_sums_words(n)]
+  uint64_t* bits = nullptr;      // [nw]: root flags, 64 vertices per word
+  uint32_t* rank = nullptr;      // [nw + 1]: roots in the words before, total last
+  uint32_t* scan_sums = nullptr; // [scan_sums_words(nw)]
   int64_t* bounds = nullptr;     // [vertex blocks + 1]: first edge of each block's range
 };
 int64_t agg_scratch_words(int32_t n);
@@ -179,16 +180,10 @@ void mesh_build(agc_context* c, Mesh& m, int32_t n_verts, int64_t n_elems, const
 void assemble_fine(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
                    int32_t out_dtype, Matrix& out, Matrix* out32 = nullptr, bool reuse_upper = false);
 // reuse_upper (float64 only): the fine upper blocks are already in the
-// workspace (upper_async + upper_join, or an assembly just before)
+// workspace (an assembly of the same element blocks just before)
 void assemble_coarse(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
                      const int32_t* map, int32_t n_c, int32_t out_dtype, Matrix& out,
                      Matrix* out32 = nullptr, bool reuse_upper = false);
-// The fine upper blocks of float64 element blocks gathered on the context's
-// second stream, after the work already on its stream; upper_join makes the
-// context's stream wait for them.  The gather needs no map, so it runs while
-// the aggregation does.
-void upper_async(agc_context* c, const Mesh& m, const double* elem_h);
-void upper_join(agc_context* c);
 // A = P^T H P in the flat 3-block layout of `am` (float64 sums; out32 as for
 // assemble_coarse)
 void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* elem_h, const AffineMap& am,
@@ -234,8 +229,6 @@ struct agc_context {
   // rtol in quarter decades): the first chunk of the next such solve
   // (chunking never changes the iterates)
   std::map<std::tuple<int32_t, int32_t, int32_t>, int32_t> pcg_last;
-  hipStream_t aux = nullptr;    // second stream (default priority) for work that overlaps the main one
-  hipEvent_t fork = nullptr, join = nullptr;
   agc::Matrix solve_a;         // matrices reused across agc_solve calls
   agc::Matrix solve_a64;
   agc::Matrix solve_fine;      // the fine system for post-coarsening
