@@ -275,6 +275,11 @@ typedef struct {
   const double* g;         /* [n_verts][3] float64 gradient                    */
   const double* rest;      /* [n_verts][3] float64 rest positions; needed only
                               with opts.affine_threshold > 0                  */
+  const double* diag_lb;   /* [n_verts] float64 or NULL: d_v > 0 with
+                              H >= diag(d) (x) I_3, e.g. the lumped masses
+                              over h^2 when H = M / h^2 + K with K positive
+                              semidefinite; enables the certified error
+                              bound (agc_solve_info.err_bound)               */
 } agc_problem;
 
 typedef struct {
@@ -301,6 +306,12 @@ typedef struct {
                           get 12 DoF (adaptive affine embedding, as in
                           agc_assemble_coarse_affine; the paper uses 32);
                           0 = 3 DoF everywhere                               */
+  double target_err;   /* > 0 (needs prob.diag_lb, affine_threshold = 0):
+                          after reaching rtol, keep iterating from the
+                          current iterate, with rtol tightened by the ratio
+                          of the bound to the target, until err_bound <=
+                          target_err (AGC_ERR_NOT_CONVERGED when max_iter
+                          ends it first); 0 = stop at rtol                   */
 } agc_solve_opts;
 
 typedef struct {
@@ -322,6 +333,15 @@ typedef struct {
   int32_t n_affine;       /* coarse nodes with 12 DoF                          */
   int32_t n_blocks;       /* 3x3 block rows of the coarse system: n_coarse
                              + 3 n_affine                                     */
+  double err_bound;       /* with prob.diag_lb and affine_threshold = 0: a
+                             bound on ||P x_c - x*||_2 / ||P x_c||_2, x* =
+                             P A_c^-1 P^T g the exact coarsened solution (H^-1
+                             g for coarsen = 0), from the float64 residual
+                             r_c = b_c - A_c x_c: A_c >= diag(D_c) (x) I_3
+                             with D_c the sum of d over the members of c, so
+                             ||P e||_2 <= sqrt(sum_c |r_c|^2 / D_c / min d);
+                             it bounds the coarse solve, before any
+                             post-coarsening; -1 when not available          */
 } agc_solve_info;
 
 /* One Newton linear solve, steps in the order of Alg. overview (mapping,

@@ -57,13 +57,13 @@ class BadInput(AgcError):
 
 class agc_problem(ctypes.Structure):
     _fields_ = [("mesh", c_void_p), ("n_edges", c_int64), ("edges", c_void_p), ("tags", c_void_p),
-                ("elem_H", c_void_p), ("g", c_void_p), ("rest", c_void_p)]
+                ("elem_H", c_void_p), ("g", c_void_p), ("rest", c_void_p), ("diag_lb", c_void_p)]
 
 
 class agc_solve_opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("coarsen", c_int32), ("rtol", c_double), ("max_iter", c_int32),
                 ("inner_rtol", c_double), ("max_refine", c_int32), ("timing", c_int32), ("post_iters", c_int32),
-                ("affine_threshold", c_int32)]
+                ("affine_threshold", c_int32), ("target_err", c_double)]
 
 
 class agc_solve_info(ctypes.Structure):
@@ -71,7 +71,7 @@ class agc_solve_info(ctypes.Structure):
                 ("rel_res", c_double), ("ms_aggregate", c_float), ("ms_assemble", c_float),
                 ("ms_pcg", c_float), ("ms_prolong", c_float), ("spmv_launches", c_int32), ("ms_spmv", c_float),
                 ("post_iters", c_int32), ("fine_rel_res", c_double), ("fine_rel_res0", c_double), ("ms_post", c_float),
-                ("n_affine", c_int32), ("n_blocks", c_int32)]
+                ("n_affine", c_int32), ("n_blocks", c_int32), ("err_bound", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -449,12 +449,12 @@ def agc_restrict(ctx: Context, map_: torch.Tensor, n_coarse: int, v: torch.Tenso
 
 
 def make_opts(precision=AGC_PREC_FP64, coarsen=1, rtol=1e-10, max_iter=20000, inner_rtol=1e-4, max_refine=20,
-              timing=0, post_iters=0, affine_threshold=0) -> agc_solve_opts:
+              timing=0, post_iters=0, affine_threshold=0, target_err=0.0) -> agc_solve_opts:
     return agc_solve_opts(int(precision), int(coarsen), float(rtol), int(max_iter), float(inner_rtol),
-                          int(max_refine), int(timing), int(post_iters), int(affine_threshold))
+                          int(max_refine), int(timing), int(post_iters), int(affine_threshold), float(target_err))
 
 
-def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None) -> agc_problem:
+def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None, diag_lb=None) -> agc_problem:
     ctx = mesh.ctx
     m = 0 if edges is None else edges.shape[0]
     if edges is not None:
@@ -464,11 +464,13 @@ def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None) -> agc_problem:
     _dev(g, torch.float64, (mesh.n_verts, 3), "g", ctx.device)
     if rest is not None:
         _dev(rest, torch.float64, (mesh.n_verts, 3), "rest", ctx.device)
-    prob = agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g), _ptr(rest))
+    if diag_lb is not None:
+        _dev(diag_lb, torch.float64, (mesh.n_verts,), "diag_lb", ctx.device)
+    prob = agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g), _ptr(rest), _ptr(diag_lb))
     # The struct holds raw device pointers that every later call reads: it
     # keeps the tensors (and the mesh) alive, or a temporary passed here would
     # be freed and its memory handed to the next allocation of that size.
-    prob._keep = (mesh, edges, tags, elem_H, g, rest)
+    prob._keep = (mesh, edges, tags, elem_H, g, rest, diag_lb)
     return prob
 
 

@@ -456,6 +456,111 @@ void restrict_sorted(agc_context* c, int32_t n, int32_t n_c, const uint32_t* mem
   seg_reduce<3, double, uint32_t, RestrictOp>(c, mkeys, n, op, (uint32_t*)nullptr, false, "rst.seg");
 }
 
+// ------------------------------------------------------- error bound
+
+struct MassOp {   // D_c = sum of d over the members of c, in member order
+  const uint32_t* members;
+  const double* d;
+  double* out;
+  __device__ void load(int64_t k, double x[1]) const { x[0] = d[members[k]]; }
+  __device__ void store(int64_t s, const double x[1]) const { out[s] = x[0]; }
+  __device__ void add(int64_t s, const double x[1]) const { out[s] += x[0]; }
+};
+
+// Per workgroup: sum over coarse nodes of |r_c|^2 / D_c, min over vertices
+// of d_v, sum over vertices of |x_c[map v]|^2 (map null: identity).
+constexpr unsigned kCertGrid = 512;
+__global__ __launch_bounds__(kWG) void k_cert_part(const double* __restrict__ dc, const double* __restrict__ r_c,
+                                                   int32_t n_c, const double* __restrict__ d,
+                                                   const int32_t* __restrict__ map, const double* __restrict__ x_c,
+                                                   int32_t n, double* __restrict__ part, unsigned* err) {
+  __shared__ double lds[2 * kWaves];
+  __shared__ double lmin[kWaves];
+  double t[2] = {0.0, 0.0};
+  double mn = INFINITY;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n_c; i += (int64_t)gridDim.x * kWG) {
+    const double D = dc[i];
+    bad |= !(D > 0.0 && D < INFINITY);
+    const double a = r_c[3 * i], b = r_c[3 * i + 1], e = r_c[3 * i + 2];
+    t[0] += (a * a + b * b + e * e) / D;
+  }
+  for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n; v += (int64_t)gridDim.x * kWG) {
+    const double dv = d[v];
+    bad |= !(dv > 0.0 && dv < INFINITY);
+    mn = dv < mn ? dv : mn;
+    const int64_t c = map ? map[v] : v;
+    const double a = x_c[3 * c], b = x_c[3 * c + 1], e = x_c[3 * c + 2];
+    t[1] += a * a + b * b + e * e;
+  }
+  if (bad) atomicOr(err, kErrDiagLb);
+  wg_sum_all<2>(t, lds);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const double q = __shfl_xor(mn, o);
+    mn = q < mn ? q : mn;
+  }
+  if (lane_id() == 0) lmin[threadIdx.x / kWave] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = lmin[0];
+    for (int w = 1; w < kWaves; ++w) m = lmin[w] < m ? lmin[w] : m;
+    part[blockIdx.x] = t[0];
+    part[kCertGrid + blockIdx.x] = m;
+    part[2 * kCertGrid + blockIdx.x] = t[1];
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_cert_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double lds[2 * kWaves];
+  __shared__ double lmin[kWaves];
+  double t[2] = {0.0, 0.0};
+  double mn = INFINITY;
+  for (unsigned i = threadIdx.x; i < kCertGrid; i += kWG) {
+    t[0] += part[i];
+    t[1] += part[2 * kCertGrid + i];
+    mn = part[kCertGrid + i] < mn ? part[kCertGrid + i] : mn;
+  }
+  wg_sum_all<2>(t, lds);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const double q = __shfl_xor(mn, o);
+    mn = q < mn ? q : mn;
+  }
+  if (lane_id() == 0) lmin[threadIdx.x / kWave] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = lmin[0];
+    for (int w = 1; w < kWaves; ++w) m = lmin[w] < m ? lmin[w] : m;
+    out[0] = t[0];
+    out[1] = m;
+    out[2] = t[1];
+  }
+}
+
+Certificate certify(agc_context* c, int32_t n, int32_t n_c, const int32_t* map, const uint32_t* members,
+                    const uint32_t* mkeys, const double* d, const double* x_c, const double* r_c) {
+  const double* dc = d;
+  if (map) {
+    double* D = c->ws.get<double>("cert.dc", n_c);
+    MassOp op{members, d, D};
+    seg_reduce<1, double, uint32_t, MassOp>(c, mkeys, n, op, (uint32_t*)nullptr, false, "cert.seg");
+    dc = D;
+  }
+  double* part = c->ws.get<double>("cert.part", 3 * kCertGrid + 3);
+  k_clear_u32<<<1, 1, 0, c->stream>>>(c->d_err);
+  k_cert_part<<<kCertGrid, kWG, 0, c->stream>>>(dc, r_c, n_c, d, map, x_c, n, part, c->d_err);
+  k_cert_final<<<1, kWG, 0, c->stream>>>(part, part + 3 * kCertGrid);
+  AGC_LAUNCH_CHECK();
+  double* h = (double*)c->h_pcg;   // pinned scratch; no PCG is in flight here
+  AGC_HIP(hipMemcpyAsync(h, part + 3 * kCertGrid, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  err_throw(err_fetch(c));   // synchronises
+  Certificate out;
+  out.bound = sqrt(h[0] / h[1]);
+  out.x_norm = sqrt(h[2]);
+  return out;
+}
+
 __global__ void k_prolong(const int32_t* __restrict__ map, int32_t n, int32_t n_c, const double* __restrict__ xc,
                           double* __restrict__ x, unsigned* err) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {

@@ -67,6 +67,8 @@ void validate_opts(const agc_solve_opts* o) {
   AGC_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
   AGC_REQUIRE(o->post_iters >= 0, "post_iters must be >= 0");
   AGC_REQUIRE(o->affine_threshold >= 0, "affine_threshold must be >= 0");
+  AGC_REQUIRE(o->target_err >= 0.0 && o->target_err < 1.0, "target_err must be in [0, 1)");
+  AGC_REQUIRE(o->target_err == 0.0 || o->affine_threshold == 0, "target_err needs affine_threshold = 0");
   if (o->precision == AGC_PREC_MIXED) {
     AGC_REQUIRE(o->inner_rtol > 0.0 && o->inner_rtol < 1.0, "inner_rtol must be in (0, 1)");
     AGC_REQUIRE(o->max_refine >= 1, "max_refine must be >= 1");
@@ -551,6 +553,30 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   tm.mark();                                                   // 1
   double* x_c = R.map ? c->ws.get<double>("solve.xc", 3 * (int64_t)R.blocks()) : x;
   SolveResult res = coarse_solve(c, p, o, R, p->g, x_c, &tm);  // marks 2 after assembly
+  // certified error of P x_c; with target_err, more iterations until it holds
+  double err_bound = -1.0;
+  if (p->diag_lb && !R.am) {
+    const int64_t n3c = 3 * (int64_t)R.blocks();
+    const double* r_c = c->ws.get<double>("solve.rc", n3c);
+    auto rel_bound = [&]() {
+      const agc::Certificate ct = agc::certify(c, n, R.n_c, R.map, R.members, R.mkeys, p->diag_lb, x_c, r_c);
+      return ct.x_norm > 0.0 ? ct.bound / ct.x_norm : (ct.bound > 0.0 ? INFINITY : 0.0);
+    };
+    err_bound = rel_bound();
+    while (o->target_err > 0.0 && err_bound > o->target_err && res.converged && res.iters < o->max_iter) {
+      const double f = o->target_err / err_bound;
+      const double rtol2 = res.rel * (f < 0.01 ? 0.01 : (f > 0.5 ? 0.5 : f));
+      const SolveResult more = coarse_iterate(c, o, n3c, x_c, rtol2, o->max_iter - res.iters, true);
+      res.iters += more.iters;
+      res.refine += more.refine;
+      res.rel = more.rel;
+      res.converged = more.converged;
+      err_bound = rel_bound();
+    }
+    if (o->target_err > 0.0 && err_bound > o->target_err) res.converged = false;
+  } else {
+    AGC_REQUIRE(o->target_err == 0.0, "target_err needs prob.diag_lb");
+  }
   tm.mark();                                                   // 3
   if (R.map) {
     agc::err_reset(c);
@@ -599,10 +625,11 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
     info->fine_rel_res = fine_rel;
     info->fine_rel_res0 = fine_rel0;
     info->ms_post = tm.ms(4, 5);
+    info->err_bound = err_bound;
   }
   if (!res.converged)
-    throw Error(AGC_ERR_NOT_CONVERGED, "coarse PCG did not reach rtol within max_iter / max_refine: x holds P times "
-                                       "the last coarse iterate");
+    throw Error(AGC_ERR_NOT_CONVERGED, "coarse PCG did not reach rtol (or target_err) within max_iter / max_refine: "
+                                       "x holds P times the last coarse iterate");
   API_END(c)
 }
 

@@ -129,7 +129,8 @@ class Workspace {
 
 // Bits of the per-call device error word.
 enum : unsigned { kErrRange = 1u, kErrTag = 2u, kErrElem = 4u, kErrMap = 8u, kErrNoDiag = 16u,
-                  kErrNotSPD = 32u, kErrDegenerate = 64u, kErrUnused = 128u };
+                  kErrNotSPD = 32u, kErrDegenerate = 64u, kErrUnused = 128u,
+                  kErrDiagLb = 256u };
 
 inline unsigned grid_blocks(int64_t n) {   // grid for a grid-stride loop over n items
   int64_t b = (n + kWG - 1) / kWG;

@@ -137,6 +137,19 @@ int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edge
 // the same with scratch from the context's workspace
 int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags,
                   int32_t* map);
+// Certified error of x = P x_c from its float64 residual r_c = b_c - A_c x_c
+// and a lower bound d of H's diagonal per vertex (H >= diag(d) (x) I_3, e.g.
+// the lumped masses over h^2): A_c >= diag(D_c) with D_c the sum of d over
+// the members of c, so the error e_c satisfies ||e_c||_D <= ||r_c||_{D^-1},
+// and ||P e_c||_2 <= ||P e_c||_d / sqrt(min d) = ||e_c||_D / sqrt(min d).
+// map null: the fine system (D = d).  Synchronises; AGC_ERR_BAD_INPUT for a
+// d_v that is not positive and finite.
+struct Certificate {
+  double bound = 0.0;    // bound on ||P x_c - P x_c*||_2
+  double x_norm = 0.0;   // ||P x_c||_2
+};
+Certificate certify(agc_context* c, int32_t n, int32_t n_c, const int32_t* map, const uint32_t* members,
+                    const uint32_t* mkeys, const double* d, const double* x_c, const double* r_c);
 // members[k]: vertices sorted by (map, id); mkeys[k] = map[members[k]]
 void group_members(agc_context* c, int32_t n, const int32_t* map, int32_t n_c, uint32_t* members,
                    uint32_t* mkeys);

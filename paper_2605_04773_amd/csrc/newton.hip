@@ -97,6 +97,11 @@ __global__ void k_nw_vptr(const uint32_t* __restrict__ key, int64_t m, int32_t n
 }
 
 // m_v = sum over the corners of v of rho V_e / 4, in element order
+__global__ void k_nw_scale(const double* __restrict__ a, double s, int64_t n, double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = s * a[i];
+}
+
 __global__ void k_nw_mass(const uint32_t* __restrict__ vptr, const uint32_t* __restrict__ corner,
                           const double* __restrict__ vol, double rho, int32_t n, double* __restrict__ mass) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -507,6 +512,12 @@ agc_status agc_newton_step(agc_context* c, agc_newton* nw, const agc_newton_opts
   agc_solve_opts so = opts->solve;
   so.coarsen = opts->coarsen ? 1 : 0;
   so.timing = 0;
+  double* dlb = nullptr;   // the certified stop (target_err) needs a lower bound of the proxy's diagonal
+  if (so.target_err > 0.0) {
+    dlb = c->ws.get<double>("nw.dlb", nw->n);
+    k_nw_scale<<<grid_blocks(nw->n), kWG, 0, c->stream>>>((const double*)nw->mass.p, 1.0 / (h * h), nw->n, dlb);
+    AGC_LAUNCH_CHECK();
+  }
   for (int it = 0; it < opts->max_newton; ++it) {
     auto t0 = clock::now();
     nw_physics(c, nw, b, xcur, xhat, b.g, b.H);
@@ -528,6 +539,7 @@ agc_status agc_newton_step(agc_context* c, agc_newton* nw, const agc_newton_opts
     pr.elem_H = b.H;
     pr.g = b.g;
     pr.rest = (const double*)nw->rest.p;
+    pr.diag_lb = dlb;   // m_v / h^2: the proxy is M / h^2 plus positive semidefinite blocks
     agc_solve_info si{};
     const agc_status st = agc_solve(c, &pr, &so, sol, nullptr, &si);
     if (st != AGC_OK && st != AGC_ERR_NOT_CONVERGED) throw Error(st, c->err);

@@ -252,6 +252,7 @@ void err_throw(unsigned bits) {
   if (bits & kErrElem) m += " element with a repeated or out-of-range vertex;";
   if (bits & kErrMap) m += " map value out of range;";
   if (bits & kErrUnused) m += " a coarse label in [0, n_coarse) has no member;";
+  if (bits & kErrDiagLb) m += " diag_lb not positive and finite;";
   if (bits & kErrNoDiag) m += " row without a diagonal block;";
   if (bits & kErrDegenerate) m += " rest element with zero volume;";
   int code = AGC_ERR_BAD_INPUT;
