@@ -162,6 +162,18 @@ agc_status agc_aggregate(agc_context* ctx, int32_t n_verts, int64_t n_edges,
                          const int32_t* edges, const uint8_t* tags,
                          int32_t* map, int32_t* n_coarse);
 
+/* agc_aggregate for callers that cannot allocate device memory during the
+ * call (code under graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as agc_aggregate; its
+ * scratch is a fixed array of the library on each GPU (18.1 MB, held until
+ * the process ends), so it allocates nothing, host or device.  n_verts must
+ * be <= 4194304 (AGC_ERR_INVALID_ARG otherwise).  All calls on one GPU share
+ * that array: calls that overlap in time on one GPU (from several threads,
+ * contexts or streams) race and give wrong maps; serialise them. */
+agc_status agc_aggregate_noalloc(agc_context* ctx, int32_t n_verts, int64_t n_edges,
+                                 const int32_t* edges, const uint8_t* tags,
+                                 int32_t* map, int32_t* n_coarse);
+
 /* ---------------------------------------------------- (b) coarse system */
 
 /* Galerkin coarse system (Sec. 4.1 "Algebraic Coarsening and System

@@ -28,7 +28,7 @@ AGC_PREC_FP64, AGC_PREC_MIXED = 0, 1
 
 EXPORTS = (
     "agc_create", "agc_set_stream", "agc_set_allocator", "agc_destroy", "agc_last_error", "agc_version",
-    "agc_mesh_create", "agc_mesh_destroy", "agc_mesh_info", "agc_aggregate",
+    "agc_mesh_create", "agc_mesh_destroy", "agc_mesh_info", "agc_aggregate", "agc_aggregate_noalloc",
     "agc_assemble_coarse", "agc_assemble_fine", "agc_matrix_destroy", "agc_matrix_info",
     "agc_matrix_copy", "agc_spmv", "agc_pcg", "agc_prolongate", "agc_restrict", "agc_solve",
     "agc_solve_backward", "agc_time_spmv", "agc_tagger_create", "agc_tagger_destroy", "agc_tag_edges",
@@ -120,6 +120,7 @@ def _load():
         "agc_mesh_destroy": (S, [P, P]),
         "agc_mesh_info": (S, [P, POINTER(c_int32), POINTER(c_int64), POINTER(c_int64)]),
         "agc_aggregate": (S, [P, c_int32, c_int64, P, P, P, POINTER(c_int32)]),
+        "agc_aggregate_noalloc": (S, [P, c_int32, c_int64, P, P, P, POINTER(c_int32)]),
         "agc_tagger_create": (S, [P, c_int32, c_int64, P, P, c_int64, P, POINTER(c_void_p)]),
         "agc_tagger_destroy": (S, [P, P]),
         "agc_assemble_coarse_affine": (S, [P, P, P, P, P, P, c_int32, c_int32, POINTER(c_void_p), P,
@@ -325,6 +326,19 @@ def agc_aggregate(ctx: Context, n_verts: int, edges: torch.Tensor, tags: torch.T
     nc = c_int32()
     _check(ctx.h, _lib.agc_aggregate(ctx.h, int(n_verts), int(m), _ptr(edges), _ptr(tags), _ptr(mp), byref(nc)))
     return mp, nc.value
+
+
+def agc_aggregate_noalloc(ctx: Context, n_verts: int, edges: torch.Tensor, tags: torch.Tensor,
+                          map_out: torch.Tensor):
+    """agc_aggregate into the caller's map, with the library's fixed scratch (no allocation)."""
+    m = edges.shape[0]
+    _dev(edges, torch.int32, (m, 2), "edges", ctx.device)
+    _dev(tags, torch.uint8, (m,), "tags", ctx.device)
+    _dev(map_out, torch.int32, (n_verts,), "map", ctx.device)
+    nc = c_int32()
+    _check(ctx.h, _lib.agc_aggregate_noalloc(ctx.h, int(n_verts), int(m), _ptr(edges), _ptr(tags), _ptr(map_out),
+                                             byref(nc)))
+    return map_out, nc.value
 
 
 def agc_assemble_coarse_affine(ctx: Context, mesh: Mesh, elem_H: torch.Tensor, rest: torch.Tensor, g,

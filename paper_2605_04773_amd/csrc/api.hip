@@ -226,6 +226,7 @@ agc_status agc_create(agc_context** out, int32_t device, void* stream) {
     AGC_HIP(hipMalloc(&c->d_pcg, sizeof(agc::PcgState)));
     AGC_HIP(hipHostMalloc(&c->h_pcg, sizeof(agc::PcgState), hipHostMallocDefault));
     for (auto& e : c->ev) AGC_HIP(hipEventCreate(&e));
+    agc::noalloc_setup(device);
   } catch (const Error& e) {
     agc_destroy(c);
     return e.code;

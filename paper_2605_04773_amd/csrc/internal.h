@@ -134,6 +134,8 @@ AggScratch agg_scratch_carve(uint32_t* base, int32_t n);
 // map and n_coarse with the given scratch; allocates nothing (synchronises)
 int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags,
                        int32_t* map, const AggScratch& s);
+// device address of the no-allocation scratch array on `device` (current), looked up once per device
+void noalloc_setup(int device);
 // the same with scratch from the context's workspace
 int32_t aggregate(agc_context* c, int32_t n, int64_t m, const int32_t* edges, const uint8_t* tags,
                   int32_t* map);
