@@ -1,13 +1,14 @@
 // BSR 3x3 SpMV and 3x3 block-Jacobi PCG (Alg. overview, solve step;
 // Sec. 5.1 "Preconditioners").
 //
-// SpMV is nonzero-balanced: workgroup w owns blocks [1024 w, 1024 w + 1024),
-// four consecutive blocks per thread, whatever the row lengths.  A coarse
+// SpMV is nonzero-balanced: workgroup w owns a tile of consecutive blocks
+// (two per thread for a float64 matrix, four for float32: 512 or 1024 per
+// tile), whatever the row lengths.  A coarse
 // matrix has one hub row per giant aggregate (tens of thousands of blocks)
 // next to rows of ~13, so splitting by rows would leave most of the chip
 // idle behind one wave.  Values are stored as nine planes (stride padded to
-// 64 blocks), so a thread's four values of one plane are one 16- or 32-byte
-// load and a wave's loads are contiguous.  Rows are summed inside a thread in
+// 64 blocks), so a thread's values of one plane are one or two 16-byte loads
+// and a wave's loads are contiguous.  Rows are summed inside a thread in
 // order, then across the threads of a wave by a DPP segmented scan, then
 // across the four waves through LDS (one barrier per tile).  A row that
 // crosses workgroups leaves one partial per workgroup in `carry`, and the
@@ -41,50 +42,86 @@
 
 namespace agc {
 
-#ifndef AGC_SPMV_ITEMS
-#define AGC_SPMV_ITEMS 4
+// Consecutive blocks per SpMV thread, by value type (a multiple of 2); a
+// workgroup's tile is kWG times that.  Two float64 blocks per thread keep the
+// kernel at 76 VGPRs (six waves per SIMD) instead of 120 (four): measured
+// 160 instead of 193 us per launch on the 10.4 M-block coarse matrix of the
+// 128^3 grid, and 416 instead of 504 us on its fine matrix.
+#ifndef AGC_SPMV_ITEMS_F64
+#define AGC_SPMV_ITEMS_F64 2
 #endif
-constexpr int kItems = AGC_SPMV_ITEMS;   // consecutive blocks per thread (a multiple of 4)
-static_assert(kItems % 4 == 0, "blocks per thread: a multiple of 4");
-constexpr int kTile = kWG * kItems;   // blocks per SpMV workgroup
+#ifndef AGC_SPMV_ITEMS_F32
+#define AGC_SPMV_ITEMS_F32 4
+#endif
+#ifndef AGC_SPMV_NT_F64
+#define AGC_SPMV_NT_F64 1
+#endif
+#ifndef AGC_SPMV_NT_F32
+#define AGC_SPMV_NT_F32 1
+#endif
+template <class T>
+struct Shape {
+  static constexpr int items = sizeof(T) == 8 ? AGC_SPMV_ITEMS_F64 : AGC_SPMV_ITEMS_F32;
+  static constexpr bool nt = sizeof(T) == 8 ? AGC_SPMV_NT_F64 : AGC_SPMV_NT_F32;
+  static constexpr int64_t tile = (int64_t)kWG * items;
+  static_assert(items % 2 == 0, "blocks per thread: a multiple of 2");
+};
+inline int64_t tile_of(int32_t dtype) { return dtype == AGC_F64 ? Shape<double>::tile : Shape<float>::tile; }
 
 // ------------------------------------------------------------ loads
 
-// Matrix loads stream: with the non-temporal hint they do not push the
-// gathered vectors out of L2.
-#ifndef AGC_SPMV_NT
-#define AGC_SPMV_NT 1
-#endif
+// Matrix loads stream.  With the non-temporal hint they do not push the
+// gathered vectors out of L2; per value type (NT = the Shape's nt), since
+// it was measured faster for the float32 matrix and slower for the float64
+// one (whose larger stream fills the queues either way).
 typedef int32_t vi4 __attribute__((ext_vector_type(4)));
+typedef int32_t vi2 __attribute__((ext_vector_type(2)));
 typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef float vf2 __attribute__((ext_vector_type(2)));
 typedef double vd2 __attribute__((ext_vector_type(2)));
-template <class V>
+template <bool NT, class V>
 __device__ __forceinline__ V stream_load(const V* p) {
-#if AGC_SPMV_NT
-  return __builtin_nontemporal_load(p);
-#else
-  return *p;
-#endif
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
 }
+template <bool NT>
 __device__ __forceinline__ void load4(const int32_t* p, int32_t o[4]) {
-  const vi4 v = stream_load(reinterpret_cast<const vi4*>(p));
+  const vi4 v = stream_load<NT>(reinterpret_cast<const vi4*>(p));
   o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
+template <bool NT>
 __device__ __forceinline__ void load4(const float* p, float o[4]) {
-  const vf4 v = stream_load(reinterpret_cast<const vf4*>(p));
+  const vf4 v = stream_load<NT>(reinterpret_cast<const vf4*>(p));
   o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
+template <bool NT>
 __device__ __forceinline__ void load4(const double* p, double o[4]) {
-  const vd2 a = stream_load(reinterpret_cast<const vd2*>(p));
-  const vd2 b = stream_load(reinterpret_cast<const vd2*>(p) + 1);
+  const vd2 a = stream_load<NT>(reinterpret_cast<const vd2*>(p));
+  const vd2 b = stream_load<NT>(reinterpret_cast<const vd2*>(p) + 1);
   o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
+template <bool NT>
+__device__ __forceinline__ void load2(const int32_t* p, int32_t o[2]) {
+  const vi2 v = stream_load<NT>(reinterpret_cast<const vi2*>(p));
+  o[0] = v.x; o[1] = v.y;
+}
+template <bool NT>
+__device__ __forceinline__ void load2(const float* p, float o[2]) {
+  const vf2 v = stream_load<NT>(reinterpret_cast<const vf2*>(p));
+  o[0] = v.x; o[1] = v.y;
+}
+template <bool NT>
+__device__ __forceinline__ void load2(const double* p, double o[2]) {
+  const vd2 a = stream_load<NT>(reinterpret_cast<const vd2*>(p));
+  o[0] = a.x; o[1] = a.y;
+}
 
-// kItems consecutive values, kItems / 4 vector loads
-template <class T>
-__device__ __forceinline__ void load_items(const T* p, T (&o)[kItems]) {
+// I consecutive values: I / 4 four-wide loads, then a two-wide one if I % 4 == 2
+template <bool NT, class T, int I>
+__device__ __forceinline__ void load_items(const T* p, T (&o)[I]) {
 #pragma unroll
-  for (int h = 0; h < kItems / 4; ++h) load4(p + 4 * h, o + 4 * h);
+  for (int h = 0; h < I / 4; ++h) load4<NT>(p + 4 * h, o + 4 * h);
+  if constexpr (I % 4 == 2) load2<NT>(p + 4 * (I / 4), o + 4 * (I / 4));
 }
 
 // The vector the SpMV multiplies, stored in V (double, or float for the
@@ -107,6 +144,7 @@ using GatherX = Gather<double>;
 // the previous kernel.  Blocks past nnzb carry row INT32_MAX and column 0.
 template <class T>
 struct Quad {
+  static constexpr int kItems = Shape<T>::items;
   int32_t r[kItems], c[kItems];
   T a[9][kItems];
   int32_t next_row;   // row of the block after the thread's last one; INT32_MAX at the tile end
@@ -124,13 +162,15 @@ struct Quad {
 template <class T>
 __device__ __forceinline__ void load_quad_index(int64_t w, const int32_t* __restrict__ ri,
                                                 const int32_t* __restrict__ col, int64_t nnzb, Quad<T>& q) {
+  constexpr int kItems = Shape<T>::items;
+  constexpr int64_t kTile = Shape<T>::tile;
   const int64_t t0 = w * kTile;
   const int64_t t1 = (t0 + kTile < nnzb) ? t0 + kTile : nnzb;
   const int64_t k0 = t0 + (int64_t)threadIdx.x * kItems;
   const int64_t kl = k0 < nnzb ? k0 : 0;
   int32_t r4[kItems], c4[kItems];
-  load_items(ri + kl, r4);
-  load_items(col + kl, c4);
+  load_items<Shape<T>::nt>(ri + kl, r4);
+  load_items<Shape<T>::nt>(col + kl, c4);
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const bool in = k0 + j < nnzb;
@@ -152,10 +192,11 @@ __device__ __forceinline__ void load_quad_index(int64_t w, const int32_t* __rest
 template <class T>
 __device__ __forceinline__ void load_quad_vals(int64_t w, const T* __restrict__ vals, int64_t nnzb, int64_t stride,
                                                Quad<T>& q) {
-  const int64_t k0 = w * kTile + (int64_t)threadIdx.x * kItems;
+  constexpr int kItems = Shape<T>::items;
+  const int64_t k0 = w * Shape<T>::tile + (int64_t)threadIdx.x * kItems;
   const int64_t kl = k0 < nnzb ? k0 : 0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) load_items(vals + (int64_t)i * stride + kl, q.a[i]);
+  for (int i = 0; i < 9; ++i) load_items<Shape<T>::nt>(vals + (int64_t)i * stride + kl, q.a[i]);
   // the loads above are issued before the gathers that follow
   __builtin_amdgcn_sched_barrier(0);
 }
@@ -185,6 +226,7 @@ struct TileLds {
 template <class T, class G, bool DOT>
 __device__ __forceinline__ double spmv_tile(int64_t w, const Quad<T>& q, const G& g, double* __restrict__ y,
                                             double* __restrict__ carry, TileLds& L) {
+  constexpr int kItems = Shape<T>::items;
   const unsigned lane = lane_id(), wave = threadIdx.x / kWave;
   double v[kItems][3];
   double dot = 0.0;
@@ -315,7 +357,8 @@ constexpr int kCarryBatch = 16;
 // q = y[r] corrected for a row whose blocks may span several tiles (rs, re:
 // its block range): then q is the last partial of its first tile plus the
 // first partials of the later ones, added in tile order.
-__device__ __forceinline__ void row_fix(int64_t rs, int64_t re, const double* __restrict__ carry, double q[3]) {
+__device__ __forceinline__ void row_fix(int64_t rs, int64_t re, const double* __restrict__ carry, double q[3],
+                                        int64_t kTile) {
   const int64_t w0 = rs / kTile, w1 = (re - 1) / kTile;
   if (re <= rs) {
     q[0] = q[1] = q[2] = 0.0;
@@ -348,7 +391,7 @@ __device__ __forceinline__ void row_fix(int64_t rs, int64_t re, const double* __
 // order: per lane in tile order, then by a butterfly.  Few registers are
 // live, so the rare hub row does not lower the occupancy of the caller.
 __device__ __forceinline__ void row_fix_wave(bool in, int64_t rs, int64_t re, const double* __restrict__ carry,
-                                             double q[3]) {
+                                             double q[3], int64_t kTile) {
   const int32_t w0 = (int32_t)(rs / kTile), w1 = (int32_t)((re - 1) / kTile);
   if (in && re <= rs) q[0] = q[1] = q[2] = 0.0;
   const bool split = in && re > rs && w0 != w1;
@@ -385,10 +428,10 @@ __device__ __forceinline__ void row_fix_wave(bool in, int64_t rs, int64_t re, co
 
 // q[r] for a row whose blocks may span several tiles.
 __device__ __forceinline__ void row_result(const int32_t* __restrict__ rp, const double* __restrict__ y,
-                                           const double* __restrict__ carry, int64_t r, double q[3]) {
+                                           const double* __restrict__ carry, int64_t r, double q[3], int64_t kTile) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) q[i] = y[3 * r + i];   // issued with the row pointers; used unless split
-  row_fix(rp[r], rp[r + 1], carry, q);
+  row_fix(rp[r], rp[r + 1], carry, q, kTile);
 }
 
 template <class T>
@@ -404,8 +447,10 @@ __global__ __launch_bounds__(kWG) void k_spmv(const int32_t* __restrict__ col, c
 }
 
 // rows that cross tiles: y[r] = sum of their partials in tile order
+template <class T>
 __global__ __launch_bounds__(kWG) void k_spmv_fix(const int32_t* __restrict__ rp, int32_t n,
                                                   const double* __restrict__ carry, double* __restrict__ y) {
+  constexpr int64_t kTile = Shape<T>::tile;
   const int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (r >= n) return;
   const int64_t rs = rp[r], re = rp[r + 1];
@@ -415,20 +460,20 @@ __global__ __launch_bounds__(kWG) void k_spmv_fix(const int32_t* __restrict__ rp
   }
   if (rs / kTile == (re - 1) / kTile) return;
   double q[3];
-  row_result(rp, y, carry, r, q);
+  row_result(rp, y, carry, r, q, kTile);
 #pragma unroll
   for (int i = 0; i < 3; ++i) y[3 * r + i] = q[i];
 }
 
 static double* spmv_carry(agc_context* c, const Matrix& a) {
-  const int64_t tiles = (a.nnzb + kTile - 1) / kTile;
+  const int64_t tiles = (a.nnzb + tile_of(a.dtype) - 1) / tile_of(a.dtype);
   return c->ws.get<double>("spmv.carry", tiles * 6 + 6);
 }
 
 void spmv(agc_context* c, const Matrix& a, const double* x, double* y) {
   if (a.n == 0) return;
   double* carry = spmv_carry(c, a);
-  const unsigned tiles = blocks_for(a.nnzb, kTile);
+  const unsigned tiles = blocks_for(a.nnzb, tile_of(a.dtype));
   if (a.nnzb > 0) {
     if (a.dtype == AGC_F64)
       k_spmv<double><<<tiles, kWG, 0, c->stream>>>(a.ci(), a.ri(), (const double*)a.vals.p, a.nnzb, a.stride, x, y,
@@ -438,7 +483,8 @@ void spmv(agc_context* c, const Matrix& a, const double* x, double* y) {
                                                  carry);
     AGC_LAUNCH_CHECK();
   }
-  k_spmv_fix<<<blocks_for(a.n, kWG), kWG, 0, c->stream>>>(a.rp(), a.n, carry, y);
+  if (a.dtype == AGC_F64) k_spmv_fix<double><<<blocks_for(a.n, kWG), kWG, 0, c->stream>>>(a.rp(), a.n, carry, y);
+  else k_spmv_fix<float><<<blocks_for(a.n, kWG), kWG, 0, c->stream>>>(a.rp(), a.n, carry, y);
   AGC_LAUNCH_CHECK();
 }
 
@@ -780,7 +826,7 @@ __global__ __launch_bounds__(kWG) AGC_UPDATE_OCC void k_pcg_update(int64_t j, co
   t[3] = part_finish(pa, ga, part[3]);
   wg_sum_all<4>(t, lds_a);
   if (stop_scalars(j, t, st, in_state, rtol)) return;
-  row_fix_wave(in, rs, re, carry, wv);
+  row_fix_wave(in, rs, re, carry, wv, Shape<Z>::tile);
   const double gamma = t[0];
   double beta = 0.0, den = t[3];
   if (j > 0) {
@@ -864,7 +910,7 @@ int pcg(agc_context* c, const Matrix& a, const double* b, double* x, double rtol
   void* sv = zvec("pcg.s");
   double* w = c->ws.get<double>("pcg.w", n3);
   const unsigned gr = blocks_for(n, kWG);
-  const unsigned gs = blocks_for(a.nnzb, kTile);
+  const unsigned gs = blocks_for(a.nnzb, tile_of(a.dtype));
   // update partials, double-buffered by parity of j: iteration j reads pbs[j%2]
   double* pbs[2] = {c->ws.get<double>("pcg.pb0", 3 * part_stride(gr)),
                     c->ws.get<double>("pcg.pb1", 3 * part_stride(gr))};
