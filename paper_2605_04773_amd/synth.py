@@ -174,8 +174,12 @@ def elastic_blocks(pos, tets, rot, mu, lam, rho, h, out=None, chunk=1 << 11, pro
         vol, grads = shape_gradients(pos, tets[e])
         # R K0 R^T from the rotated gradients q_a = R grad N_a (R R^T = I):
         # block (a,b) = V (mu (grad N_a . grad N_b) I + mu q_b q_a^T + lam q_a q_b^T)
-        q = grads @ np.swapaxes(rot[e], -1, -2)                        # (m,4,3)
-        gg = grads @ np.swapaxes(grads, -1, -2)                        # (m,4,4)
+        # elementwise products summed in a fixed order (no BLAS: the same bits in every thread)
+        r = rot[e]
+        q = (grads[:, :, None, 0] * r[:, None, :, 0] + grads[:, :, None, 1] * r[:, None, :, 1]
+             + grads[:, :, None, 2] * r[:, None, :, 2])                # (m,4,3): q_a = R grad N_a
+        gg = (grads[:, :, None, 0] * grads[:, None, :, 0] + grads[:, :, None, 1] * grads[:, None, :, 1]
+              + grads[:, :, None, 2] * grads[:, None, :, 2])           # (m,4,4)
         blk = (mu * q.transpose(0, 2, 1)[:, None, :, :, None]) * q[:, :, None, None, :]
         blk += (lam * q)[:, :, :, None, None] * q[:, None, None, :, :]
         idx = np.arange(3)
@@ -216,9 +220,16 @@ def fourier_field(rng: np.random.Generator, n_modes: int = 4):
 
 
 def eval_field(field, pos, shift=None):
+    """The field at each position, summed in a fixed order without BLAS (whose
+    rounding can depend on how many threads call it), so that tags drawn from
+    it are the same on every host and in every thread."""
     p = pos if shift is None else pos - shift[None, :]
-    arg = 2.0 * math.pi * (p @ field["k"].T) + field["phase"][None, :]
-    return np.cos(arg) @ field["amp"]
+    out = np.zeros(p.shape[0])
+    for m in range(field["amp"].shape[0]):
+        k = field["k"][m]
+        arg = 2.0 * math.pi * (p[:, 0] * k[0] + p[:, 1] * k[1] + p[:, 2] * k[2]) + field["phase"][m]
+        out += field["amp"][m] * np.cos(arg)
+    return out
 
 
 def rank_tags(values: np.ndarray, frac: float) -> np.ndarray:
