@@ -227,6 +227,8 @@ __global__ __launch_bounds__(kCcThreads) void k_cc_local(const int32_t* __restri
 // all lanes of a wave take part in the ballots.
 constexpr int kCrossCache = 512;   // remembered pairs per workgroup (direct-mapped)
 
+constexpr int kCrossBatch = 4;     // edges per lane loaded together
+
 __global__ __launch_bounds__(kWG) void k_cc_cross(const int32_t* __restrict__ edges, const uint8_t* __restrict__ tags,
                                                   int64_t m, int32_t* parent, int32_t n,
                                                   const int64_t* __restrict__ bounds, unsigned* err) {
@@ -236,52 +238,68 @@ __global__ __launch_bounds__(kWG) void k_cc_cross(const int32_t* __restrict__ ed
   const int64_t per = (m + gridDim.x - 1) / gridDim.x;
   const int64_t e_lo = (int64_t)blockIdx.x * per, e_hi = e_lo + per < m ? e_lo + per : m;
   const unsigned lane = lane_id();
-  for (int64_t base = e_lo; base < e_hi; base += kWG) {
-    const int64_t e = base + threadIdx.x;
-    bool want = false;
-    int32_t lo = 0, hi = 0;
-    if (e < e_hi) {
-      const int2 uv = reinterpret_cast<const int2*>(edges)[e];
-      const int32_t u = uv.x, v = uv.y;
-      const uint8_t t = tags[e];
-      if (u < 0 || u >= n || v < 0 || v >= n) {
-        atomicOr(err, kErrRange);
-      } else if (t > 1) {
-        atomicOr(err, kErrTag);
-      } else if (t == 1 && u != v) {
-        want = true;
-        const int32_t bu = u >> kCcLog;
-        if (bu == (v >> kCcLog)) {            // joined by pass one if e lies in its block's range
-          const int64_t s0 = bounds[bu], s1 = bounds[bu + 1];
-          want = !(e >= (s0 < s1 ? s0 : s1) && e < (s0 < s1 ? s1 : s0));
-        }
-        if (want) {   // the ends' parents: their local roots from pass one, or ancestors of them
-          const int32_t pu = ld_parent(parent, u), pv = ld_parent(parent, v);
-          lo = pu < pv ? pu : pv;
-          hi = pu < pv ? pv : pu;
-          want = pu != pv;
+  for (int64_t base = e_lo; base < e_hi; base += (int64_t)kWG * kCrossBatch) {
+    // kCrossBatch edges per lane: their ids and tags, then the parents of
+    // their ends, each group of loads issued together (indices past the
+    // range repeat its last edge and are masked)
+    int2 uv[kCrossBatch];
+    uint8_t tg[kCrossBatch];
+#pragma unroll
+    for (int j = 0; j < kCrossBatch; ++j) {
+      const int64_t e = base + (int64_t)j * kWG + threadIdx.x;
+      const int64_t ec = e < e_hi ? e : e_hi - 1;
+      uv[j] = reinterpret_cast<const int2*>(edges)[ec];
+      tg[j] = tags[ec];
+    }
+    bool want[kCrossBatch];
+    int32_t pu[kCrossBatch], pv[kCrossBatch];
+#pragma unroll
+    for (int j = 0; j < kCrossBatch; ++j) {
+      const int64_t e = base + (int64_t)j * kWG + threadIdx.x;
+      const int32_t u = uv[j].x, v = uv[j].y;
+      want[j] = false;
+      if (e < e_hi) {
+        if (u < 0 || u >= n || v < 0 || v >= n) {
+          atomicOr(err, kErrRange);
+        } else if (tg[j] > 1) {
+          atomicOr(err, kErrTag);
+        } else if (tg[j] == 1 && u != v) {
+          want[j] = true;
+          const int32_t bu = u >> kCcLog;
+          if (bu == (v >> kCcLog)) {            // joined by pass one if e lies in its block's range
+            const int64_t s0 = bounds[bu], s1 = bounds[bu + 1];
+            want[j] = !(e >= (s0 < s1 ? s0 : s1) && e < (s0 < s1 ? s1 : s0));
+          }
         }
       }
+      // the ends' parents: their local roots from pass one, or ancestors of them
+      pu[j] = want[j] ? ld_parent(parent, u) : 0;
+      pv[j] = want[j] ? ld_parent(parent, v) : 0;
     }
-    uint64_t pend = __ballot(want);
-    while (pend) {
-      const int leader = __ffsll((unsigned long long)pend) - 1;
-      const int32_t h = __shfl(hi, leader), l = __shfl(lo, leader);
-      pend &= ~__ballot(want && hi == h && lo == l);
-      if ((int)lane == leader) {
-        const uint64_t key = ((uint64_t)(uint32_t)h << 32) | (uint32_t)l;
-        const uint32_t slot = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 55) & (kCrossCache - 1);
-        if (seen[slot] != key) {
-          int32_t ru = find_root_coherent(parent, l), rv = find_root_coherent(parent, h);
-          while (ru != rv) {
-            const int32_t a = ru < rv ? ru : rv, b = ru < rv ? rv : ru;
-            const int32_t old = atomicCAS(parent + b, b, a);
-            if (old == b) break;                    // hooked b below a
-            // b stopped being a root meanwhile: continue from its new root
-            const int32_t r = find_root_coherent(parent, old);
-            if (ru == b) ru = r; else rv = r;
+#pragma unroll
+    for (int j = 0; j < kCrossBatch; ++j) {
+      const int32_t lo = pu[j] < pv[j] ? pu[j] : pv[j], hi = pu[j] < pv[j] ? pv[j] : pu[j];
+      const bool w = want[j] && pu[j] != pv[j];
+      uint64_t pend = __ballot(w);
+      while (pend) {
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const int32_t h = __shfl(hi, leader), l = __shfl(lo, leader);
+        pend &= ~__ballot(w && hi == h && lo == l);
+        if ((int)lane == leader) {
+          const uint64_t key = ((uint64_t)(uint32_t)h << 32) | (uint32_t)l;
+          const uint32_t slot = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 55) & (kCrossCache - 1);
+          if (seen[slot] != key) {
+            int32_t ru = find_root_coherent(parent, l), rv = find_root_coherent(parent, h);
+            while (ru != rv) {
+              const int32_t a = ru < rv ? ru : rv, b = ru < rv ? rv : ru;
+              const int32_t old = atomicCAS(parent + b, b, a);
+              if (old == b) break;                    // hooked b below a
+              // b stopped being a root meanwhile: continue from its new root
+              const int32_t r = find_root_coherent(parent, old);
+              if (ru == b) ru = r; else rv = r;
+            }
+            seen[slot] = key;
           }
-          seen[slot] = key;
         }
       }
     }
