@@ -292,6 +292,18 @@ typedef struct {
                               over h^2 when H = M / h^2 + K with K positive
                               semidefinite; enables the certified error
                               bound (agc_solve_info.err_bound)               */
+  int64_t n_contacts;      /* elements of this call only, beside the mesh's:
+                              the contact stencils the paper finds anew every
+                              Newton iteration (Sec. 3; Alg. overview), each
+                              a 12x12 block over 4 vertices whose pairs enter
+                              the Galerkin sum on each call without the mesh's
+                              static plan (0 = none)                          */
+  const int32_t* contact_verts; /* [n_contacts][4] int32, 4 distinct ids in
+                              [0, n_verts) (AGC_ERR_BAD_INPUT otherwise)      */
+  const double* contact_H; /* [n_contacts][144] float64 row-major, symmetric;
+                              with contacts, post_iters and affine_threshold
+                              must be 0 and agc_solve_backward is not
+                              available (AGC_ERR_INVALID_ARG)                 */
 } agc_problem;
 
 typedef struct {

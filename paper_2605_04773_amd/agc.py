@@ -57,7 +57,8 @@ class BadInput(AgcError):
 
 class agc_problem(ctypes.Structure):
     _fields_ = [("mesh", c_void_p), ("n_edges", c_int64), ("edges", c_void_p), ("tags", c_void_p),
-                ("elem_H", c_void_p), ("g", c_void_p), ("rest", c_void_p), ("diag_lb", c_void_p)]
+                ("elem_H", c_void_p), ("g", c_void_p), ("rest", c_void_p), ("diag_lb", c_void_p),
+                ("n_contacts", c_int64), ("contact_verts", c_void_p), ("contact_H", c_void_p)]
 
 
 class agc_solve_opts(ctypes.Structure):
@@ -468,7 +469,8 @@ def make_opts(precision=AGC_PREC_FP64, coarsen=1, rtol=1e-10, max_iter=20000, in
                           int(max_refine), int(timing), int(post_iters), int(affine_threshold), float(target_err))
 
 
-def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None, diag_lb=None) -> agc_problem:
+def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None, diag_lb=None, contacts=None) -> agc_problem:
+    """contacts: (verts [n][4] int32, H [n][144] float64) assembled on each call beside the mesh's elements."""
     ctx = mesh.ctx
     m = 0 if edges is None else edges.shape[0]
     if edges is not None:
@@ -480,11 +482,18 @@ def make_problem(mesh: Mesh, edges, tags, elem_H, g, rest=None, diag_lb=None) ->
         _dev(rest, torch.float64, (mesh.n_verts, 3), "rest", ctx.device)
     if diag_lb is not None:
         _dev(diag_lb, torch.float64, (mesh.n_verts,), "diag_lb", ctx.device)
-    prob = agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g), _ptr(rest), _ptr(diag_lb))
+    cv, ch = (None, None) if contacts is None else contacts
+    nx = 0
+    if cv is not None:
+        nx = cv.shape[0]
+        _dev(cv, torch.int32, (nx, 4), "contact_verts", ctx.device)
+        _dev(ch, torch.float64, (nx, 144), "contact_H", ctx.device)
+    prob = agc_problem(mesh.h, int(m), _ptr(edges), _ptr(tags), _ptr(elem_H), _ptr(g), _ptr(rest), _ptr(diag_lb),
+                       int(nx), _ptr(cv), _ptr(ch))
     # The struct holds raw device pointers that every later call reads: it
     # keeps the tensors (and the mesh) alive, or a temporary passed here would
     # be freed and its memory handed to the next allocation of that size.
-    prob._keep = (mesh, edges, tags, elem_H, g, rest, diag_lb)
+    prob._keep = (mesh, edges, tags, elem_H, g, rest, diag_lb, cv, ch)
     return prob
 
 

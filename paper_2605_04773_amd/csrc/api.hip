@@ -81,6 +81,16 @@ void validate_problem(const agc_problem* p) {
   AGC_REQUIRE(((uintptr_t)p->elem_H & 15) == 0, "elem_H must be 16-byte aligned");
   AGC_REQUIRE(p->n_edges >= 0, "n_edges < 0");
   AGC_REQUIRE(((uintptr_t)p->edges & 7) == 0, "edges must be 8-byte aligned");
+  AGC_REQUIRE(p->n_contacts >= 0 && (p->n_contacts == 0 || (p->contact_verts && p->contact_H)),
+              "contact elements need ids and blocks");
+}
+
+agc::Contacts contacts_of(const agc_problem* p) {
+  agc::Contacts x;
+  x.n = p->n_contacts;
+  x.verts = p->contact_verts;
+  x.H = p->contact_H;
+  return x;
 }
 
 // Solves A_c x_c = b_c for the matrix assembled from the problem.
@@ -192,9 +202,20 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   const bool mixed = o->precision == AGC_PREC_MIXED;
   agc::Matrix& A64 = c->solve_a64;
   agc::Matrix* A32 = mixed ? &c->solve_a : nullptr;
-  if (R.am) agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32);
-  else if (R.map) agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, R.n_c, AGC_F64, A64, A32);
-  else agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, A64, A32);
+  const agc::Contacts x = contacts_of(p);
+  if (R.am) {
+    agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32);
+  } else if (R.map) {
+    agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, R.n_c, AGC_F64, A64, A32, false, x);
+  } else if (x.n > 0) {
+    // the fine system with this call's contact pairs: the coarse assembly with the identity map
+    int32_t* ident = c->ws.get<int32_t>("solve.ident", mesh.n_verts);
+    k_iota_i32<<<gsb(mesh.n_verts), agc::kWG, 0, c->stream>>>(ident, mesh.n_verts);
+    AGC_LAUNCH_CHECK();
+    agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, ident, mesh.n_verts, AGC_F64, A64, A32, false, x);
+  } else {
+    agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, A64, A32);
+  }
   if (tm) tm->mark();
   return coarse_iterate(c, o, n3c, x_c, o->rtol, o->max_iter, false);
 }
@@ -522,6 +543,8 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   const agc::Mesh& mesh = p->mesh->m;
   const int32_t n = mesh.n_verts;
   AGC_REQUIRE(o->coarsen == 0 || p->n_edges == 0 || (p->edges && p->tags), "edges/tags null");
+  AGC_REQUIRE(p->n_contacts == 0 || (o->post_iters == 0 && o->affine_threshold == 0),
+              "contact elements need post_iters = 0 and affine_threshold = 0");
   Timer tm(c, o->timing != 0);
   struct KernelTiming {   // on for this call only, also when it throws
     agc_context* c;
@@ -642,6 +665,7 @@ agc_status agc_solve_backward(agc_context* c, const agc_problem* p, const agc_so
   validate_opts(o);
   AGC_REQUIRE(o->post_iters == 0 && o->affine_threshold == 0,
               "post_iters and affine_threshold must be 0 for the derivative of the coarsened solve");
+  AGC_REQUIRE(p->n_contacts == 0, "the derivative is taken with respect to the mesh's elements only: no contacts");
   AGC_REQUIRE(x && w && dg, "null pointer");
   const agc::Mesh& mesh = p->mesh->m;
   const int32_t n = mesh.n_verts;

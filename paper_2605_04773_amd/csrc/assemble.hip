@@ -659,19 +659,80 @@ __global__ void k_coarse_keys(const int32_t* __restrict__ fr, const int32_t* __r
   }
 }
 
+// Upper pair q (0..9) of an element: (0,0) (0,1) (0,2) (0,3) (1,1) (1,2)
+// (1,3) (2,2) (2,3) (3,3).
+__device__ __forceinline__ void upper_pair(int q, int& a, int& b) {
+  a = q < 4 ? 0 : (q < 7 ? 1 : (q < 9 ? 2 : 3));
+  b = a + (q < 4 ? q : (q < 7 ? q - 4 : (q < 9 ? q - 7 : 0)));
+}
+
+// Coarse upper keys of the per-call elements (contact stencils found anew
+// every Newton iteration), item nf + 10 e + q for upper pair q = (a, b) of
+// element e: its fine block (v_a, v_b) is sub-block (a, b) of the element
+// block, oriented and folded as in k_coarse_keys.  Flags element ids out of
+// range or repeated (kErrElem) and map values out of range (kErrMap).
+__global__ void k_contact_keys(const int32_t* __restrict__ xv, int64_t nx, int32_t n, const int32_t* __restrict__ map,
+                               int32_t n_c, int64_t nf, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                               unsigned* err) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 10 * nx; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = t / 10;
+    int a, b;
+    upper_pair((int)(t - 10 * e), a, b);
+    const int32_t va = xv[4 * e + a], vb = xv[4 * e + b];
+    const int64_t item = nf + t;
+    if (va < 0 || va >= n || vb < 0 || vb >= n || (a != b && va == vb)) {
+      atomicOr(err, kErrElem);
+      keys[item] = 0;
+      vals[item] = (uint32_t)(item * 4);
+      continue;
+    }
+    const int32_t ca = map[va], cb = map[vb];
+    if (ca < 0 || ca >= n_c || cb < 0 || cb >= n_c) {
+      atomicOr(err, kErrMap);
+      keys[item] = 0;
+      vals[item] = (uint32_t)(item * 4);
+      continue;
+    }
+    uint32_t o;
+    uint64_t key;
+    if (ca < cb) { key = (uint64_t)ca * n_c + cb; o = 0; }
+    else if (ca > cb) { key = (uint64_t)cb * n_c + ca; o = 1; }
+    else { key = (uint64_t)ca * n_c + ca; o = (a == b) ? 0u : 2u; }
+    keys[item] = key;
+    vals[item] = (uint32_t)(item * 4) | o;
+  }
+}
+
 template <class Acc>
 struct CoarseOp {
   const uint32_t* payload;
   const Acc* F;
   int64_t nf;
-  Acc* U;   // planes of stride nf
+  Acc* U;   // planes of stride us
+  int64_t us;
+  const double* xH;   // per-call element blocks (items nf + 10 e + q), or null
+  // every field named at each use: the affine assembly reduces the fine items
+  // only, into planes of stride nf
+  CoarseOp(const uint32_t* payload_, const Acc* F_, int64_t nf_, Acc* U_, int64_t us_, const double* xH_)
+      : payload(payload_), F(F_), nf(nf_), U(U_), us(us_), xH(xH_) {}
   __device__ void load(int64_t k, Acc v[9]) const {
     const uint32_t code = payload[k];
     const int64_t f = code >> 2;
     const uint32_t o = code & 3u;
     Acc b[9];
+    if (f < nf) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) b[i] = F[(int64_t)i * nf + f];
+      for (int i = 0; i < 9; ++i) b[i] = F[(int64_t)i * nf + f];
+    } else {
+      const int64_t t = f - nf, e = t / 10;
+      int pa, pb;
+      upper_pair((int)(t - 10 * e), pa, pb);
+      const double* h = xH + e * 144 + 36 * pa + 3 * pb;   // rows 3 pa.., columns 3 pb..
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) b[3 * r + q] = (Acc)h[12 * r + q];
+    }
     if (o == 0) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) v[i] = b[i];
@@ -689,37 +750,44 @@ struct CoarseOp {
   }
   __device__ void store(int64_t s, const Acc v[9]) const {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) U[(int64_t)i * nf + s] = v[i];
+    for (int i = 0; i < 9; ++i) U[(int64_t)i * us + s] = v[i];
   }
   __device__ void add(int64_t s, const Acc v[9]) const {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) U[(int64_t)i * nf + s] += v[i];
+    for (int i = 0; i < 9; ++i) U[(int64_t)i * us + s] += v[i];
   }
 };
 
 template <class Acc>
 static void coarse_impl(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, const int32_t* map,
-                        int32_t n_c, Matrix& out, Matrix* out32, bool reuse_upper) {
+                        int32_t n_c, Matrix& out, Matrix* out32, bool reuse_upper, const Contacts& x) {
   const int64_t nf = m.nf;
+  const int64_t ni = nf + 10 * x.n;   // items: the fine upper blocks, then the per-call elements' upper pairs
+  AGC_REQUIRE(ni < (int64_t(1) << 30), "too many fine blocks and contact pairs");
   Acc* F;
   if constexpr (sizeof(Acc) == 8) F = reuse_upper ? upper_ready(c, m) : fine_upper<Acc>(c, m, eh, h_dtype);
   else F = fine_upper<Acc>(c, m, eh, h_dtype);
-  uint64_t* k1 = c->ws.get<uint64_t>("asm.k1", nf);
-  uint64_t* k2 = c->ws.get<uint64_t>("asm.k2", nf);
-  uint32_t* v1 = c->ws.get<uint32_t>("asm.v1", nf);
-  uint32_t* v2 = c->ws.get<uint32_t>("asm.v2", nf);
+  uint64_t* k1 = c->ws.get<uint64_t>("asm.k1", ni);
+  uint64_t* k2 = c->ws.get<uint64_t>("asm.k2", ni);
+  uint32_t* v1 = c->ws.get<uint32_t>("asm.v1", ni);
+  uint32_t* v2 = c->ws.get<uint32_t>("asm.v2", ni);
   err_reset(c);
   k_coarse_keys<<<grid_stride_blocks(nf), kWG, 0, c->stream>>>((const int32_t*)m.fu_row.p, (const int32_t*)m.fu_col.p,
                                                               nf, map, n_c, k1, v1, c->d_err);
   AGC_LAUNCH_CHECK();
+  if (x.n > 0) {
+    k_contact_keys<<<grid_stride_blocks(10 * x.n), kWG, 0, c->stream>>>(x.verts, x.n, m.n_verts, map, n_c, nf, k1, v1,
+                                                                        c->d_err);
+    AGC_LAUNCH_CHECK();
+  }
   const int nb = bits_for((uint64_t)n_c * (uint64_t)n_c - 1);
-  const bool alt = radix_sort_u64(c, k1, v1, k2, v2, nf, nb, "asm.sort");
+  const bool alt = radix_sort_u64(c, k1, v1, k2, v2, ni, nb, "asm.sort");
   uint64_t* sk = alt ? k2 : k1;
   uint32_t* sv = alt ? v2 : v1;
   uint64_t* uk = alt ? k1 : k2;   // free buffer for the unique keys
-  Acc* U = c->ws.get<Acc>(sizeof(Acc) == 8 ? "asm.U64" : "asm.U32", 9 * nf);
-  CoarseOp<Acc> op{sv, F, nf, U};
-  const int64_t nu = seg_reduce<9, Acc, uint64_t, CoarseOp<Acc>>(c, sk, nf, op, uk, true, "asm.seg");
+  Acc* U = c->ws.get<Acc>(sizeof(Acc) == 8 ? "asm.U64" : "asm.U32", 9 * ni);
+  CoarseOp<Acc> op(sv, F, nf, U, ni, x.H);
+  const int64_t nu = seg_reduce<9, Acc, uint64_t, CoarseOp<Acc>>(c, sk, ni, op, uk, true, "asm.seg");
   int32_t* ur = c->ws.get<int32_t>("asm.ur", nu);
   int32_t* uc = c->ws.get<int32_t>("asm.uc", nu);
   k_split_keys<<<grid_stride_blocks(nu), kWG, 0, c->stream>>>(uk, nu, (uint64_t)n_c, ur, uc);
@@ -733,17 +801,19 @@ static void coarse_impl(agc_context* c, const Mesh& m, const void* eh, int32_t h
   err_throw(err_fetch(c));
   out.set_nnzb(nnz);
   float* v32 = companion32(out, out32);
-  k_fill_vals<Acc><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>(src, nnz, U, nf, (Acc*)out.vals.p, out.stride, v32);
+  k_fill_vals<Acc><<<blocks_for(nnz, kWG), kWG, 0, c->stream>>>(src, nnz, U, ni, (Acc*)out.vals.p, out.stride, v32);
   AGC_LAUNCH_CHECK();
 }
 
 void assemble_coarse(agc_context* c, const Mesh& m, const void* eh, int32_t h_dtype, const int32_t* map,
-                     int32_t n_c, int32_t out_dtype, Matrix& out, Matrix* out32, bool reuse_upper) {
+                     int32_t n_c, int32_t out_dtype, Matrix& out, Matrix* out32, bool reuse_upper,
+                     const Contacts& x) {
   AGC_REQUIRE(n_c >= 1 && n_c <= m.n_verts, "n_coarse out of range");
   AGC_REQUIRE(!out32 || out_dtype == AGC_F64, "a float32 companion needs a float64 matrix");
   AGC_REQUIRE(!reuse_upper || (out_dtype == AGC_F64 && h_dtype == AGC_F64), "reused fine blocks are float64");
-  if (out_dtype == AGC_F64) coarse_impl<double>(c, m, eh, h_dtype, map, n_c, out, out32, reuse_upper);
-  else coarse_impl<float>(c, m, eh, h_dtype, map, n_c, out, nullptr, false);
+  AGC_REQUIRE(x.n == 0 || (x.verts && x.H), "contact elements need ids and blocks");
+  if (out_dtype == AGC_F64) coarse_impl<double>(c, m, eh, h_dtype, map, n_c, out, out32, reuse_upper, x);
+  else coarse_impl<float>(c, m, eh, h_dtype, map, n_c, out, nullptr, false, x);
 }
 
 // ------------------------------------------------ affine embedding (Eq. 4)
@@ -970,7 +1040,7 @@ void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* eh, con
   double* U9 = c->ws.get<double>("aasm.U9", 9 * nf);   // CoarseOp writes planes of stride nf
   int64_t nu9 = 0;
   if (split > 0) {
-    CoarseOp<double> op{sv, F, nf, U9};
+    CoarseOp<double> op(sv, F, nf, U9, nf, nullptr);
     nu9 = seg_reduce<9, double, uint64_t, CoarseOp<double>>(c, sk, split, op, uk, true, "aasm.seg9");
   }
   // the pairs with a 12-DoF node: four passes of four sub-blocks

@@ -194,11 +194,19 @@ void mesh_build(agc_context* c, Mesh& m, int32_t n_verts, int64_t n_elems, const
 // the same element blocks left in the workspace instead of gathering them again
 void assemble_fine(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
                    int32_t out_dtype, Matrix& out, Matrix* out32 = nullptr, bool reuse_upper = false);
+// Per-call elements beside the mesh's (contact stencils found anew every
+// Newton iteration): [n][4] ids and [n][144] float64 row-major blocks, keyed
+// at the coarse level on each call instead of entering the static plan.
+struct Contacts {
+  int64_t n = 0;
+  const int32_t* verts = nullptr;
+  const double* H = nullptr;
+};
 // reuse_upper (float64 only): the fine upper blocks are already in the
 // workspace (an assembly of the same element blocks just before)
 void assemble_coarse(agc_context* c, const Mesh& m, const void* elem_h, int32_t h_dtype,
                      const int32_t* map, int32_t n_c, int32_t out_dtype, Matrix& out,
-                     Matrix* out32 = nullptr, bool reuse_upper = false);
+                     Matrix* out32 = nullptr, bool reuse_upper = false, const Contacts& x = Contacts{});
 // A = P^T H P in the flat 3-block layout of `am` (float64 sums; out32 as for
 // assemble_coarse)
 void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* elem_h, const AffineMap& am,
