@@ -161,7 +161,8 @@ __device__ void lds_union(int32_t* lp, int32_t a, int32_t b) {
 // reported by pass two.
 __global__ __launch_bounds__(kCcThreads) void k_cc_local(const int32_t* __restrict__ edges,
                                                          const uint8_t* __restrict__ tags, int64_t m, int32_t n,
-                                                         int32_t* __restrict__ parent, int64_t* __restrict__ bounds) {
+                                                         int32_t* __restrict__ parent, int64_t* __restrict__ bounds,
+                                                         unsigned* __restrict__ err) {
   __shared__ int32_t lp[kCcBlock];
   __shared__ int64_t rng[2];
   const int32_t nb = (int32_t)(((int64_t)n + kCcBlock - 1) >> kCcLog);
@@ -182,6 +183,7 @@ __global__ __launch_bounds__(kCcThreads) void k_cc_local(const int32_t* __restri
   if (threadIdx.x == 0) {
     bounds[b] = a0;
     if (b == nb - 1) bounds[nb] = m;
+    if (b == 0) *err = 0u;   // the call's error word, set by pass two only
   }
   const int64_t e0 = a0 < a1 ? a0 : a1, e1 = a0 < a1 ? a1 : a0;
   // kCcBatch edges per thread are loaded together (indices past the range
@@ -306,33 +308,91 @@ __global__ __launch_bounds__(kWG) void k_cc_cross(const int32_t* __restrict__ ed
   }
 }
 
-// Root bits: word w holds, in bit i, whether vertex 64 w + i is a root
-// (parent[v] == v: the smallest id of a component), one wave per word;
-// cnt[w] = its popcount.
-__global__ void k_cc_rootbits(const int32_t* __restrict__ parent, int32_t n, uint64_t* __restrict__ bits,
-                              uint32_t* __restrict__ cnt) {
+// Root words and their ranks within tiles of kWave words (4096 vertices),
+// one tile per workgroup: word w holds, in bit i, whether vertex 64 w + i is
+// a root (parent[v] == v: the smallest id of a component); lrank[w] = the
+// roots of the tile's words before w; tsum[t] = the roots of tile t.
+constexpr int kRootTileWords = kWave;
+constexpr int kRootWordsPerWave = kRootTileWords / kWaves;
+__global__ __launch_bounds__(kWG) void k_cc_rootrank(const int32_t* __restrict__ parent, int32_t n,
+                                                     uint64_t* __restrict__ bits, uint32_t* __restrict__ lrank,
+                                                     uint32_t* __restrict__ tsum) {
+  __shared__ uint32_t cnt[kRootTileWords];
+  const unsigned wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nw * kWave; base += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t v = base + threadIdx.x;
-    const uint64_t word = __ballot(v < n && parent[v] == (int32_t)v);
-    if (lane_id() == 0) {
-      const int64_t w = v / kWave;
-      bits[w] = word;
-      cnt[w] = (uint32_t)__popcll(word);
+  const int64_t w0 = (int64_t)blockIdx.x * kRootTileWords + wave * kRootWordsPerWave;
+  int32_t pv[kRootWordsPerWave];
+#pragma unroll
+  for (int i = 0; i < kRootWordsPerWave; ++i) {   // all loads in flight before the ballots
+    const int64_t v = (w0 + i) * kWave + lane;
+    pv[i] = v < n ? parent[v] : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < kRootWordsPerWave; ++i) {
+    const int64_t v = (w0 + i) * kWave + lane;
+    const uint64_t word = __ballot(v < n && pv[i] == (int32_t)v);
+    if (lane == 0) {
+      cnt[wave * kRootWordsPerWave + i] = (uint32_t)__popcll(word);
+      if (w0 + i < nw) bits[w0 + i] = word;
     }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const uint32_t c = cnt[lane];
+    uint32_t x = c;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d);
+      if (lane >= (unsigned)d) x += y;
+    }
+    const int64_t w = (int64_t)blockIdx.x * kRootTileWords + lane;
+    if (w < nw) lrank[w] = x - c;
+    if (lane == kWave - 1) tsum[blockIdx.x] = x;
   }
 }
 
-// map[v] = number of roots below v's root r: the roots of the words before
-// r's (rank, an exclusive scan of cnt) plus those below r in its word.
-__global__ void k_cc_label(const int32_t* __restrict__ parent, const uint64_t* __restrict__ bits,
-                           const uint32_t* __restrict__ rank, int32_t n, int32_t* __restrict__ map) {
+// Tiles whose prefix every label workgroup sums itself, in LDS: up to
+// 4096 x 4096 vertices.  Beyond, the prefix is scanned once beforehand
+// (tp: exclusive, the total at tp[tiles]).
+constexpr int64_t kLabelLdsTiles = 4096;
+
+// map[v] = number of roots below v's root r: those of the tiles before r's
+// (the exclusive prefix of tsum), of the words before r's in its tile
+// (lrank) and of the bits under r in its word.  *count = all roots.
+template <bool kLdsPrefix>
+__global__ __launch_bounds__(kWG) void k_cc_label(const int32_t* __restrict__ parent,
+                                                  const uint64_t* __restrict__ bits,
+                                                  const uint32_t* __restrict__ lrank,
+                                                  const uint32_t* __restrict__ tsum, const uint32_t* __restrict__ tp,
+                                                  int64_t tiles, int32_t n, int32_t* __restrict__ map,
+                                                  uint32_t* __restrict__ count) {
+  __shared__ uint32_t pre[kLdsPrefix ? kLabelLdsTiles : 1];
+  __shared__ uint32_t red[kWaves];
+  if constexpr (kLdsPrefix) {
+    // thread t sums tiles [t per, (t + 1) per), then the workgroup scans those sums
+    const int64_t per = (tiles + kWG - 1) / kWG;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    uint32_t sum = 0;
+    for (int64_t k = lo; k < lo + per && k < tiles; ++k) sum += tsum[k];
+    uint32_t total;
+    uint32_t off = wg_exclusive_scan(sum, red, &total);
+    for (int64_t k = lo; k < lo + per && k < tiles; ++k) {
+      pre[k] = off;
+      off += tsum[k];
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = total;
+  } else {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = tp[tiles];
+  }
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     int32_t x = (int32_t)v, p;
     while ((p = parent[x]) != x) x = p;       // read-only walk to the root
     const int32_t w = x >> 6;
+    const int32_t t = w / kRootTileWords;
     const uint64_t below = (x & 63) ? (bits[w] << (64 - (x & 63))) : 0ull;   // bits of the word under x
-    map[v] = (int32_t)(rank[w] + (uint32_t)__popcll(below));
+    const uint32_t tile_pre = kLdsPrefix ? pre[t] : tp[t];
+    map[v] = (int32_t)(tile_pre + lrank[w] + (uint32_t)__popcll(below));
   }
 }
 
@@ -349,8 +409,7 @@ int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edge
   if (n == 0) return 0;
   int32_t* parent = s.parent;
   const unsigned nb = (unsigned)(((int64_t)n + kCcBlock - 1) >> kCcLog);
-  k_clear_u32<<<1, 1, 0, c->stream>>>(c->d_err);
-  k_cc_local<<<nb, kCcThreads, 0, c->stream>>>(edges, tags, m, n, parent, s.bounds);
+  k_cc_local<<<nb, kCcThreads, 0, c->stream>>>(edges, tags, m, n, parent, s.bounds, c->d_err);
   AGC_LAUNCH_CHECK();
   if (m > 0) {
     // contiguous ranges of at least 2048 edges, up to eight workgroups per CU
@@ -359,41 +418,64 @@ int32_t aggregate_into(agc_context* c, int32_t n, int64_t m, const int32_t* edge
     k_cc_cross<<<(unsigned)g, kWG, 0, c->stream>>>(edges, tags, m, parent, n, s.bounds, c->d_err);
     AGC_LAUNCH_CHECK();
   }
-  const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
-  k_cc_rootbits<<<gs_blocks(nw * kWave), kWG, 0, c->stream>>>(parent, n, s.bits, s.rank);
+  const int64_t tiles = agg_root_tiles(n);
+  k_cc_rootrank<<<(unsigned)tiles, kWG, 0, c->stream>>>(parent, n, s.bits, s.lrank, s.tsum);
   AGC_LAUNCH_CHECK();
-  scan_u32_into(c, s.rank, s.rank, nw, s.scan_sums);
-  k_cc_label<<<gs_blocks(n), kWG, 0, c->stream>>>(parent, s.bits, s.rank, n, map);
+  // up to eight workgroups per CU walk the vertices (each sums the tile prefix once)
+  int64_t lb = ((int64_t)n + kWG - 1) / kWG;
+  if (lb > 2048) lb = 2048;
+  uint32_t* count = c->d_err + 1;   // beside the error word: one copy brings both back
+  if (tiles <= kLabelLdsTiles) {
+    k_cc_label<true><<<(unsigned)lb, kWG, 0, c->stream>>>(parent, s.bits, s.lrank, s.tsum, nullptr, tiles, n, map,
+                                                          count);
+  } else {
+    scan_u32_into(c, s.tsum, s.tp, tiles, s.scan_sums);
+    k_cc_label<false><<<(unsigned)lb, kWG, 0, c->stream>>>(parent, s.bits, s.lrank, s.tsum, s.tp, tiles, n, map,
+                                                           count);
+  }
   AGC_LAUNCH_CHECK();
-  uint32_t* h = (uint32_t*)c->h_pcg;   // pinned scratch of the context; no PCG is in flight here
-  AGC_HIP(hipMemcpyAsync(h, s.rank + nw, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-  err_throw(err_fetch(c));   // synchronises
-  return (int32_t)h[0];
+  AGC_HIP(hipMemcpyAsync(c->h_err, c->d_err, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+  AGC_HIP(hipStreamSynchronize(c->stream));
+  err_throw(c->h_err[0]);
+  return (int32_t)c->h_err[1];
 }
 
-// parent [n], root bits [nw] (64-bit), word ranks [nw + 1], scan sums,
-// bounds [nb + 1] (64-bit), each from a 256-byte boundary; nw = words of 64
-// vertices, nb = vertex blocks
+// parent [n], root bits [nw] (64-bit), in-tile word ranks [nw], tile sums
+// and their scanned prefix [tiles + 1] each, scan sums, bounds [nb + 1]
+// (64-bit), each from a 256-byte boundary; nw = words of 64 vertices, tiles
+// = root tiles of 64 words, nb = vertex blocks
 static int64_t round64(int64_t w) { return (w + 63) & ~(int64_t)63; }
+
+int64_t agg_root_tiles(int32_t n) {
+  const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
+  return (nw + kRootTileWords - 1) / kRootTileWords;
+}
 
 int64_t agg_scratch_words(int32_t n) {
   const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
+  const int64_t tiles = agg_root_tiles(n);
   const int64_t nb = ((int64_t)n + kCcBlock - 1) >> kCcLog;
-  return round64(n) + round64(2 * nw) + round64(nw + 1) + round64(scan_sums_words(nw)) + round64(2 * (nb + 1));
+  return round64(n) + round64(2 * nw) + round64(nw) + 2 * round64(tiles + 1) + round64(scan_sums_words(tiles)) +
+         round64(2 * (nb + 1));
 }
 
 AggScratch agg_scratch_carve(uint32_t* base, int32_t n) {
   const int64_t nw = ((int64_t)n + kWave - 1) / kWave;
+  const int64_t tiles = agg_root_tiles(n);
   AggScratch s;
   int64_t off = 0;
   s.parent = reinterpret_cast<int32_t*>(base);
   off = round64((int64_t)n);
   s.bits = reinterpret_cast<uint64_t*>(base + off);
   off += round64(2 * nw);
-  s.rank = base + off;
-  off += round64(nw + 1);
+  s.lrank = base + off;
+  off += round64(nw);
+  s.tsum = base + off;
+  off += round64(tiles + 1);
+  s.tp = base + off;
+  off += round64(tiles + 1);
   s.scan_sums = base + off;
-  off += round64(scan_sums_words(nw));
+  off += round64(scan_sums_words(tiles));
   s.bounds = reinterpret_cast<int64_t*>(base + off);
   return s;
 }

@@ -125,10 +125,13 @@ void scan_u32_into(agc_context* c, const uint32_t* in, uint32_t* out, int64_t n,
 struct AggScratch {
   int32_t* parent = nullptr;     // [n]
   uint64_t* bits = nullptr;      // [nw]: root flags, 64 vertices per word
-  uint32_t* rank = nullptr;      // [nw + 1]: roots in the words before, total last
-  uint32_t* scan_sums = nullptr; // [scan_sums_words(nw)]
+  uint32_t* lrank = nullptr;     // [nw]: roots in the words before, within a tile of 64 words
+  uint32_t* tsum = nullptr;      // [tiles + 1]: roots per tile
+  uint32_t* tp = nullptr;        // [tiles + 1]: exclusive prefix of tsum (very large n only)
+  uint32_t* scan_sums = nullptr; // [scan_sums_words(tiles)]
   int64_t* bounds = nullptr;     // [vertex blocks + 1]: first edge of each block's range
 };
+int64_t agg_root_tiles(int32_t n);
 int64_t agg_scratch_words(int32_t n);
 AggScratch agg_scratch_carve(uint32_t* base, int32_t n);
 // map and n_coarse with the given scratch; allocates nothing (synchronises)

@@ -1,5 +1,5 @@
 // Aggregation that allocates nothing: its scratch (parent forest, root
-// flags, scan tile sums, block bounds) is a fixed device array of this file,
+// flags and ranks, tile sums, block bounds) is a fixed device array of this file,
 // one copy per GPU, whose device address is looked up once per device when a
 // context is created there.  For callers that cannot allocate device memory
 // during the call (graph capture, tight serving loops).
@@ -10,8 +10,9 @@
 namespace agc {
 namespace {
 
-// A parent word per vertex plus root bits and ranks (3 words per 64
-// vertices), scan tile sums, block bounds and alignment slack:
+// A parent word per vertex plus root bits and in-tile ranks (3 words per 64
+// vertices), root counts per tile of 4096 vertices, block bounds and
+// alignment slack:
 // agg_scratch_words(kNoallocMaxVerts) fits (checked at set-up).  4,194,304
 // vertices: 18.1 MB per GPU, held until the process ends.
 constexpr int32_t kNoallocMaxVerts = 1 << 22;

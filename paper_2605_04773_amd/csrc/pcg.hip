@@ -59,9 +59,6 @@ namespace agc {
 #ifndef AGC_SPMV_NT_F32
 #define AGC_SPMV_NT_F32 1
 #endif
-#ifndef AGC_SPMV_KEEP_MB
-#define AGC_SPMV_KEEP_MB 0
-#endif
 template <class T>
 struct Shape {
   static constexpr int items = sizeof(T) == 8 ? AGC_SPMV_ITEMS_F64 : AGC_SPMV_ITEMS_F32;
@@ -162,7 +159,7 @@ struct Quad {
 // INT32_MAX, column 0; their values are whatever the padding holds, and the
 // SpMV zeroes their products).  No load sits under a branch, so the wait for
 // the indices is the only one before the gathers are issued.
-template <class T, bool NT = Shape<T>::nt>
+template <class T>
 __device__ __forceinline__ void load_quad_index(int64_t w, const int32_t* __restrict__ ri,
                                                 const int32_t* __restrict__ col, int64_t nnzb, Quad<T>& q) {
   constexpr int kItems = Shape<T>::items;
@@ -172,8 +169,8 @@ __device__ __forceinline__ void load_quad_index(int64_t w, const int32_t* __rest
   const int64_t k0 = t0 + (int64_t)threadIdx.x * kItems;
   const int64_t kl = k0 < nnzb ? k0 : 0;
   int32_t r4[kItems], c4[kItems];
-  load_items<NT>(ri + kl, r4);
-  load_items<NT>(col + kl, c4);
+  load_items<Shape<T>::nt>(ri + kl, r4);
+  load_items<Shape<T>::nt>(col + kl, c4);
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const bool in = k0 + j < nnzb;
@@ -192,14 +189,14 @@ __device__ __forceinline__ void load_quad_index(int64_t w, const int32_t* __rest
 }
 
 // ...and its nine value planes.
-template <class T, bool NT = Shape<T>::nt>
+template <class T>
 __device__ __forceinline__ void load_quad_vals(int64_t w, const T* __restrict__ vals, int64_t nnzb, int64_t stride,
                                                Quad<T>& q) {
   constexpr int kItems = Shape<T>::items;
   const int64_t k0 = w * Shape<T>::tile + (int64_t)threadIdx.x * kItems;
   const int64_t kl = k0 < nnzb ? k0 : 0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) load_items<NT>(vals + (int64_t)i * stride + kl, q.a[i]);
+  for (int i = 0; i < 9; ++i) load_items<Shape<T>::nt>(vals + (int64_t)i * stride + kl, q.a[i]);
   // the loads above are issued before the gathers that follow
   __builtin_amdgcn_sched_barrier(0);
 }
@@ -741,24 +738,9 @@ __global__ __launch_bounds__(kWG) AGC_SPMV_OCC void k_pcg_spmv(const int32_t* __
   // The flag is read with the index loads, before the value planes: a launch
   // after convergence then reads only the indices, and a working one does
   // not wait for the flag before it starts loading.
-#if AGC_SPMV_KEEP_MB > 0
-  // the tiles of the first AGC_SPMV_KEEP_MB MiB of values load without the
-  // non-temporal hint
-  constexpr int64_t kTileBytes = Shape<T>::tile * 9 * (int64_t)sizeof(T);
-  if (t * kTileBytes < ((int64_t)AGC_SPMV_KEEP_MB << 20)) {
-    load_quad_index<T, false>(t, ri, col, nnzb, q);
-    if (st->done) return;
-    load_quad_vals<T, false>(t, vals, nnzb, stride, q);
-  } else {
-    load_quad_index(t, ri, col, nnzb, q);
-    if (st->done) return;
-    load_quad_vals(t, vals, nnzb, stride, q);
-  }
-#else
   load_quad_index(t, ri, col, nnzb, q);
   if (st->done) return;
   load_quad_vals(t, vals, nnzb, stride, q);
-#endif
   const double d = spmv_tile<T, Gather<T>, true>(t, q, Gather<T>{z}, w, carry, L);
   if (threadIdx.x == 0) pa[t] = d;
 }

@@ -62,6 +62,12 @@ def _graphs():
     out.append(("path_cut", n, e, (np.arange(n - 1) % 7 != 0).astype(np.uint8)))
     out.append(("dups_loops", 10, np.array([[1, 1], [2, 3], [3, 2], [2, 3], [9, 9], [0, 9]]),
                 np.array([1, 1, 1, 0, 1, 1], np.uint8)))
+    # the labelling sums the roots per tile of 4096 vertices; up to 4096 tiles
+    # each workgroup sums the tiles before in LDS, beyond that one scan runs
+    # first: the largest size of the one and the smallest of the other
+    for n in (4096 * 4096, 4096 * 4096 + 1):
+        e, t = synth.random_graph(rng, n, 2_000_000, p_tag=0.7)
+        out.append((f"rand{n}_tiles", n, e, t))
     return out
 
 
