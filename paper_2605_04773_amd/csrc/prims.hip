@@ -147,9 +147,15 @@ __global__ __launch_bounds__(kWG) void k_radix_hist(const K* __restrict__ keys, 
   hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter.  Items of a tile are taken in rounds of kWG consecutive
-// keys; inside a round the rank of a key among equal digits is (earlier
-// waves' counts) + (lower lanes with the same digit, from 8 ballots).
+// Stable scatter of one tile.  Its keys and values are all loaded first.
+// The tile's count of each digit comes from the scanned histogram (the
+// difference of two neighbouring offsets), and their exclusive scan gives
+// the digit's first position in the tile.  The items are then ranked in
+// rounds of kWG consecutive keys (rank among equal digits: earlier rounds'
+// and earlier waves' counts plus the lower lanes with the same digit, from
+// eight ballots) and placed in LDS in digit order; finally the tile is
+// written out in that order, so that consecutive threads store consecutive
+// positions of one digit.
 template <class K>
 __global__ __launch_bounds__(kWG) void k_radix_scatter(const K* __restrict__ keys_in,
                                                        const uint32_t* __restrict__ vals_in,
@@ -157,23 +163,40 @@ __global__ __launch_bounds__(kWG) void k_radix_scatter(const K* __restrict__ key
                                                        uint32_t* __restrict__ vals_out, int64_t n,
                                                        int shift, const uint32_t* __restrict__ offs,
                                                        int64_t n_tiles) {
-  __shared__ uint32_t base[kRadix];
+  __shared__ K lk[kSortTile];
+  __shared__ uint32_t lv[kSortTile];
+  __shared__ uint32_t gbase[kRadix];   // global position of the digit's first item, less its tile position
+  __shared__ uint32_t run[kRadix];     // next tile position of the digit
   __shared__ uint32_t wcnt[kWaves][kRadix];
+  __shared__ uint32_t red[kWaves];
   const unsigned t = threadIdx.x;
   const unsigned wave = t / kWave;
-  base[t] = offs[(int64_t)t * n_tiles + blockIdx.x];
   const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
-  const uint64_t lt = lanemask_lt();
-  for (int r = 0; r < kSortItems; ++r) {
+  const int len = (n - tile0 < kSortTile) ? (int)(n - tile0) : kSortTile;
+  K key[kSortItems];
+  uint32_t val[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {   // past the end: the last item again, never placed
     const int64_t k = tile0 + r * kWG + t;
-    if (tile0 + r * kWG >= n) break;            // uniform across the workgroup
+    const int64_t kc = k < n ? k : n - 1;
+    key[r] = keys_in[kc];
+    val[r] = vals_in[kc];
+  }
+  const int64_t h = (int64_t)t * n_tiles + blockIdx.x;   // thread t owns digit t
+  const uint32_t g0 = offs[h];
+  uint32_t tile_total;
+  const uint32_t ls = wg_exclusive_scan(offs[h + 1] - g0, red, &tile_total);
+  gbase[t] = g0 - ls;
+  run[t] = ls;
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (r * kWG >= len) break;   // uniform across the workgroup
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wcnt[w][t] = 0;
     __syncthreads();
-    const bool valid = k < n;
-    K key = valid ? keys_in[k] : (K)0;
-    uint32_t val = valid ? vals_in[k] : 0u;
-    const unsigned digit = (unsigned)((key >> shift) & (kRadix - 1));
+    const bool valid = r * kWG + (int)t < len;
+    const unsigned digit = (unsigned)((key[r] >> shift) & (kRadix - 1));
     uint64_t match = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
@@ -185,17 +208,24 @@ __global__ __launch_bounds__(kWG) void k_radix_scatter(const K* __restrict__ key
     if (valid && rank == 0) wcnt[wave][digit] = (uint32_t)__popcll(match);
     __syncthreads();
     if (valid) {
-      uint32_t pos = base[digit] + rank;
+      uint32_t pos = run[digit] + rank;
       for (unsigned w = 0; w < wave; ++w) pos += wcnt[w][digit];
-      keys_out[pos] = key;
-      vals_out[pos] = val;
+      lk[pos] = key[r];
+      lv[pos] = val[r];
     }
     __syncthreads();
+    // column t of wcnt is read and cleared by thread t alone from here on
     uint32_t add = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) add += wcnt[w][t];
-    base[t] += add;
-    __syncthreads();
+    run[t] += add;
+  }
+  __syncthreads();
+  for (int p = (int)t; p < len; p += kWG) {
+    const K kk = lk[p];
+    const uint32_t gp = gbase[(unsigned)((kk >> shift) & (kRadix - 1))] + (uint32_t)p;
+    keys_out[gp] = kk;
+    vals_out[gp] = lv[p];
   }
 }
 
