@@ -113,6 +113,29 @@ def test_fine_with_contacts(ctx, name):
     assert e <= 1e-8 and rel(x, xs) <= 1e-10
 
 
+def test_contact_set_changes_between_calls(ctx):
+    """One context, one tet plan, three calls whose contact sets shrink
+    (all 300, the first 120, none) and a fourth with all of them again: each
+    solution matches the oracle's direct solve with the tets and that call's
+    contacts (the coarse assembly's buffers are sized per call)."""
+    import torch
+    agc = binding()
+    d = setup(ctx, "small")
+    p, nt = d["p"], d["p"]["n_tets"]
+    n = p["n_verts"]
+    x = torch.empty((n, 3), dtype=torch.float64, device=ctx.device)
+    for k in (300, 120, 0, 300):
+        q = dict(p, elem_verts=p["elem_verts"][:nt + k], elem_H=p["elem_H"][:nt + k])
+        ref = method.coarsened_solve(q, solver="dense")["x"]
+        contacts = (d["cv"][:k].contiguous(), d["ch"][:k].contiguous()) if k else None
+        prob = agc.make_problem(d["mesh_tets"], d["edges"], d["tags"], d["eh_tets"], d["g"], d["rest"],
+                                contacts=contacts)
+        agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-12, max_iter=100000), x)
+        e = rel(x.cpu().numpy(), ref)
+        log(f"[contacts] {k} contacts per call: error {e:.2e}")
+        assert e <= 1e-8
+
+
 def test_rejected(ctx):
     import torch
     agc = binding()
