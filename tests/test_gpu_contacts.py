@@ -20,6 +20,7 @@ from oracle import aggregate as oagg
 from oracle import method
 from paper_2605_04773_amd import synth
 from tests.gpu_util import binding, log
+from tests.gpu_util import problem as gpu_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -165,3 +166,69 @@ def test_rejected(ctx):
     # the context still works
     x2, _, _ = solve(ctx, d, rtol=1e-10)
     assert rel(x2, d["ref_c"]["x"]) <= 1e-7
+
+
+_full = {}
+
+
+def _full_row(ctx):
+    """The contact row at full size: a plan of the tets alone, the contact blocks per call."""
+    if "d" not in _full:
+        import torch
+        agc = binding()
+        p = gpu_problem("c3")
+        nt = p["n_tets"]
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(ctx.device, dt)
+        ev, eh = t(p["elem_verts"], torch.int32), t(p["elem_H"], torch.float64)
+        _full["d"] = {"p": p, "mesh": agc.agc_mesh_create(ctx, p["n_verts"], ev[:nt].contiguous()),
+                      "edges": t(p["edges"], torch.int32), "tags": t(p["tags"], torch.uint8),
+                      "eh": eh[:nt].contiguous(), "cv": ev[nt:].contiguous(), "ch": eh[nt:].contiguous(),
+                      "g": t(p["g"], torch.float64), "rest": t(p["pos"], torch.float64)}
+    return _full["d"]
+
+
+def _full_solve(ctx, d, **kw):
+    import torch
+    agc = binding()
+    prob = agc.make_problem(d["mesh"], d["edges"], d["tags"], d["eh"], d["g"], d["rest"], contacts=(d["cv"], d["ch"]))
+    n = d["p"]["n_verts"]
+    x = torch.empty((n, 3), dtype=torch.float64, device=ctx.device)
+    mp = torch.empty(n, dtype=torch.int32, device=ctx.device)
+    info = agc.agc_solve(ctx, prob, agc.make_opts(max_iter=50000, **kw), x, mp)
+    return x.cpu().numpy(), mp.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "fine_fp64"])
+def test_full_size_contact_row(ctx, mode):
+    """The contact row at full size (108,000 vertices, 368,640 tets, 250,000
+    contact blocks given per call): the map is the oracle's; in FP64 at rtol
+    1e-10 the oracle's matrix-free residual with every element is <= 1e-8; at
+    rtol 1e-7 the error against an FP64 reference that the oracle certifies
+    (residual and mass bound <= 1e-8) is <= 1e-5, the bars of the static plan."""
+    from tests.test_gpu_solve import _certified
+    agc = binding()
+    d = _full_row(ctx)
+    p = d["p"]
+    coarsen = 0 if mode.startswith("fine") else 1
+    if coarsen:
+        m, nc = oagg.components(p["n_verts"], p["edges"], p["tags"])
+    else:
+        m, nc = np.arange(p["n_verts"], dtype=np.int32), p["n_verts"]
+    key = ("ref", coarsen)
+    if key not in _full:
+        x_ref, mp, info = _full_solve(ctx, d, coarsen=coarsen, rtol=1e-12)
+        cert, _ = _certified(p, m, nc, x_ref)
+        log(f"[contacts] full row reference coarsen={coarsen}: iters {info.pcg_iters} certified {cert:.2e}")
+        assert np.array_equal(mp, m) and cert <= 1e-8
+        _full[key] = x_ref
+    x_ref = _full[key]
+    if mode != "mixed":
+        x, mp, info = _full_solve(ctx, d, coarsen=coarsen, rtol=1e-10)
+        _, res = _certified(p, m, nc, x)
+        log(f"[contacts] full row {mode} rtol 1e-10: iters {info.pcg_iters} oracle residual {res:.2e}")
+        assert np.array_equal(mp, m) and res <= 1e-8
+    prec = agc.AGC_PREC_MIXED if mode == "mixed" else agc.AGC_PREC_FP64
+    x, mp, info = _full_solve(ctx, d, coarsen=coarsen, precision=prec, rtol=1e-7)
+    err = rel(x, x_ref)
+    log(f"[contacts] full row {mode} rtol 1e-7: iters {info.pcg_iters} error {err:.2e}")
+    assert np.array_equal(mp, m) and err <= 1e-5
