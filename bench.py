@@ -677,6 +677,10 @@ def single_system(args, name, ctx, torch, agc, synth, with_extras, headline):
                              ("fine_fp64", solver_x(rtol=rtol_fine, coarsen=0), ref_fine)):
             ms_leg, _ = time_steps(fn, K, max(1, W // 2), torch)
             pc[leg] = {"ms_per_solve": round(float(np.mean(ms_leg)), 4), "rel_err": rel_err(fn, ref)}
+        ms_post, pinfo = time_steps(solver_x(precision=agc.AGC_PREC_MIXED, inner_rtol=args.inner_rtol, post_iters=10),
+                                    K, max(1, W // 2), torch)
+        pc["coarse_mixed_post10"] = {"ms_per_solve": round(float(np.mean(ms_post)), 4),
+                                     "fine_rel_res_before": pinfo.fine_rel_res0, "fine_rel_res_after": pinfo.fine_rel_res}
         pc["speedup_mixed_vs_fine_fp64"] = round(pc["fine_fp64"]["ms_per_solve"] / pc["coarse_mixed"]["ms_per_solve"], 3)
         pc["speedup_fp64_vs_fine_fp64"] = round(pc["fine_fp64"]["ms_per_solve"] / pc["coarse_fp64"]["ms_per_solve"], 3)
         pc["note"] = ("the mesh plan holds the tets only; the contact elements come with each call and are keyed at the "
@@ -684,7 +688,9 @@ def single_system(args, name, ctx, torch, agc, synth, with_extras, headline):
         res["contacts_per_call"] = pc
         mesh_t.close()
         log(f"[bench] {name} contacts per call: FP64 {pc['coarse_fp64']['ms_per_solve']:.2f} ms, mixed "
-            f"{pc['coarse_mixed']['ms_per_solve']:.2f} ms, fine FP64 {pc['fine_fp64']['ms_per_solve']:.2f} ms")
+            f"{pc['coarse_mixed']['ms_per_solve']:.2f} ms, fine FP64 {pc['fine_fp64']['ms_per_solve']:.2f} ms; mixed "
+            f"with 10 post-coarsening iterations {pc['coarse_mixed_post10']['ms_per_solve']:.2f} ms (fine residual "
+            f"{pinfo.fine_rel_res0:.2e} -> {pinfo.fine_rel_res:.2e})")
     if with_extras:
         res["f32_element_input"] = f32_element_input(args, p, ctx, mesh, edges, tags, eh, g, ref_coarse, rtol, torch,
                                                      agc)

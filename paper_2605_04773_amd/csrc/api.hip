@@ -543,8 +543,7 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   const agc::Mesh& mesh = p->mesh->m;
   const int32_t n = mesh.n_verts;
   AGC_REQUIRE(o->coarsen == 0 || p->n_edges == 0 || (p->edges && p->tags), "edges/tags null");
-  AGC_REQUIRE(p->n_contacts == 0 || (o->post_iters == 0 && o->affine_threshold == 0),
-              "contact elements need post_iters = 0 and affine_threshold = 0");
+  AGC_REQUIRE(p->n_contacts == 0 || o->affine_threshold == 0, "contact elements need affine_threshold = 0");
   Timer tm(c, o->timing != 0);
   struct KernelTiming {   // on for this call only, also when it throws
     agc_context* c;
@@ -613,8 +612,18 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   double fine_rel0 = 0.0, fine_rel = 0.0;
   if (o->post_iters > 0 && R.map) {
     agc::Matrix& F = c->solve_fine;
-    // the coarse assembly just gathered the fine upper blocks of these element blocks
-    agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, F, nullptr, true);
+    // the coarse assembly just gathered the fine upper blocks of these element
+    // blocks; this call's contact pairs join them through the coarse assembly
+    // with the identity map
+    const agc::Contacts xc = contacts_of(p);
+    if (xc.n > 0) {
+      int32_t* ident = c->ws.get<int32_t>("solve.ident", n);
+      k_iota_i32<<<gsb(n), agc::kWG, 0, c->stream>>>(ident, n);
+      AGC_LAUNCH_CHECK();
+      agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, ident, n, AGC_F64, F, nullptr, true, xc);
+    } else {
+      agc::assemble_fine(c, mesh, p->elem_H, AGC_F64, AGC_F64, F, nullptr, true);
+    }
     const int64_t n3 = 3 * (int64_t)n;
     double* y = c->ws.get<double>("post.y", n3);
     double* r = c->ws.get<double>("post.r", n3);

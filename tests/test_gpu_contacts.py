@@ -9,9 +9,9 @@ the tetrahedra only and the contact elements come with the problem.  The map
 is bit-exact against the oracle's components; the FP64 solutions (coarsened,
 and fine with coarsen = 0) match the oracle's direct solve of the system
 with every element; the mixed solution is within 1e-5; the solution equals
-the one with the contacts in the static plan to rounding; the certified
-bound holds; malformed contacts and the unsupported combinations are
-rejected.
+the one with the contacts in the static plan to rounding; post-coarsening
+iterates on the fine system with the contacts; the certified bound holds;
+malformed contacts and the unsupported combinations are rejected.
 """
 import numpy as np
 import pytest
@@ -114,6 +114,25 @@ def test_fine_with_contacts(ctx, name):
     assert e <= 1e-8 and rel(x, xs) <= 1e-10
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_post_coarsening_with_contacts(ctx, name):
+    """Post-coarsening (Sec. 4.3) with the contacts given per call: k fine
+    PCG iterations from x = P x_c on the fine system with every element.  The
+    oracle's textbook PCG from the GPU's own x0 gives the same x (1e-9), and
+    so does the static plan with the contacts in the mesh (1e-10)."""
+    d = setup(ctx, name)
+    k = 10
+    x0, _, _ = solve(ctx, d, rtol=1e-9)
+    x, _, info = solve(ctx, d, rtol=1e-9, post_iters=k)
+    xs, _, _ = solve(ctx, d, per_call=False, rtol=1e-9, post_iters=k)
+    ref, its = method.post_coarsen(d["p"], x0, k)
+    log(f"[contacts] {name} post-coarsening: fine residual {info.fine_rel_res0:.3e} -> {info.fine_rel_res:.3e}; "
+        f"x vs oracle {rel(x, ref):.2e}, vs static plan {rel(x, xs):.2e}")
+    assert info.post_iters == k and its == k
+    assert rel(x, ref) <= 1e-9 and rel(x, xs) <= 1e-10
+    assert info.fine_rel_res < info.fine_rel_res0
+
+
 def test_contact_set_changes_between_calls(ctx):
     """One context, one tet plan, three calls whose contact sets shrink
     (all 300, the first 120, none) and a fourth with all of them again: each
@@ -155,9 +174,8 @@ def test_rejected(ctx):
         agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-8), x)
     prob = agc.make_problem(d["mesh_tets"], d["edges"], d["tags"], d["eh_tets"], d["g"], d["rest"],
                             contacts=(d["cv"], d["ch"]))
-    for kw in (dict(post_iters=3), dict(affine_threshold=8)):
-        with pytest.raises(agc.AgcError):
-            agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-8, **kw), x)
+    with pytest.raises(agc.AgcError):
+        agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-8, affine_threshold=8), x)
     mp = torch.empty(p["n_verts"], dtype=torch.int32, device=ctx.device)
     info = agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-10), x, mp)
     with pytest.raises(agc.AgcError):
