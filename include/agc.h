@@ -301,10 +301,11 @@ typedef struct {
   const int32_t* contact_verts; /* [n_contacts][4] int32, 4 distinct ids in
                               [0, n_verts) (AGC_ERR_BAD_INPUT otherwise)      */
   const double* contact_H; /* [n_contacts][144] float64 row-major, symmetric;
-                              with contacts, affine_threshold must be 0 and
-                              agc_solve_backward is not available
+                              with contacts, affine_threshold must be 0
                               (AGC_ERR_INVALID_ARG); post-coarsening iterates
-                              on the fine system with them                    */
+                              on the fine system with them, and
+                              agc_solve_backward returns their dL/dH after
+                              the mesh's                                      */
 } agc_problem;
 
 typedef struct {
@@ -385,8 +386,10 @@ agc_status agc_solve(agc_context* ctx, const agc_problem* prob, const agc_solve_
  *   lambda_c = A_c^{-1} P^T w,  dL/dg = P lambda_c,
  *   dL/dH_e  = -(S_e P lambda_c)(S_e x)^T   (12x12, not symmetrised).
  * Only the map (and x) from the forward pass are needed; A_c is assembled
- * again, never stored.  dg: [n_verts][3] float64 out; dH: [n_elems][144]
- * float64 out, may be NULL.  opts->precision selects the solve as in
+ * again, never stored.  dg: [n_verts][3] float64 out; dH: [n_elems +
+ * n_contacts][144] float64 out, may be NULL: the mesh's elements, then the
+ * problem's contact elements (whose blocks enter A_c as in agc_solve).
+ * opts->precision selects the solve as in
  * agc_solve; opts->post_iters and opts->affine_threshold must be 0 (the
  * derivative is that of the 3-DoF coarsened solve).  The map must use every
  * label in [0, n_coarse) (AGC_ERR_BAD_INPUT otherwise).  A PCG stopped at

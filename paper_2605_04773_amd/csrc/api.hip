@@ -674,7 +674,6 @@ agc_status agc_solve_backward(agc_context* c, const agc_problem* p, const agc_so
   validate_opts(o);
   AGC_REQUIRE(o->post_iters == 0 && o->affine_threshold == 0,
               "post_iters and affine_threshold must be 0 for the derivative of the coarsened solve");
-  AGC_REQUIRE(p->n_contacts == 0, "the derivative is taken with respect to the mesh's elements only: no contacts");
   AGC_REQUIRE(x && w && dg, "null pointer");
   const agc::Mesh& mesh = p->mesh->m;
   const int32_t n = mesh.n_verts;
@@ -698,7 +697,11 @@ agc_status agc_solve_backward(agc_context* c, const agc_problem* p, const agc_so
     agc::err_reset(c);
     agc::prolongate(c, n, R.map, R.n_c, lam_c, dg);   // dL/dg = P lambda_c
   }
-  if (dH) agc::elem_outer(c, mesh, dg, x, dH);        // dL/dH_e = -(S_e P lambda_c)(S_e x)^T
+  if (dH) {                                            // dL/dH_e = -(S_e P lambda_c)(S_e x)^T
+    agc::elem_outer(c, mesh, dg, x, dH);
+    // then the call's contact elements (their ids were checked by the solve above)
+    agc::elem_outer_list(c, p->contact_verts, p->n_contacts, dg, x, dH + 144 * mesh.n_elems);
+  }
   agc::err_throw(agc::err_fetch(c));
   if (info) {
     std::memset(info, 0, sizeof(*info));

@@ -1125,12 +1125,17 @@ __global__ __launch_bounds__(kWG) void k_elem_outer(const int32_t* __restrict__ 
   }
 }
 
-void elem_outer(agc_context* c, const Mesh& m, const double* dg, const double* x, double* dh) {
-  const int64_t total = 144 * m.n_elems;
+void elem_outer_list(agc_context* c, const int32_t* ev, int64_t ne, const double* dg, const double* x, double* dh) {
+  if (ne <= 0) return;
+  const int64_t total = 144 * ne;
   int64_t b = (total + kWG - 1) / kWG;
   if (b > 262144) b = 262144;
-  k_elem_outer<<<(unsigned)b, kWG, 0, c->stream>>>((const int32_t*)m.elem_verts.p, m.n_elems, dg, x, dh);
+  k_elem_outer<<<(unsigned)b, kWG, 0, c->stream>>>(ev, ne, dg, x, dh);
   AGC_LAUNCH_CHECK();
+}
+
+void elem_outer(agc_context* c, const Mesh& m, const double* dg, const double* x, double* dh) {
+  elem_outer_list(c, (const int32_t*)m.elem_verts.p, m.n_elems, dg, x, dh);
 }
 
 }  // namespace agc

@@ -216,6 +216,8 @@ void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* elem_h,
                             Matrix& out, Matrix* out32 = nullptr, bool reuse_upper = false);
 // dH_e = -(dg_e)(x_e)^T
 void elem_outer(agc_context* c, const Mesh& m, const double* dg, const double* x, double* dh);
+// the same over a list of elements ([ne][4] ids, checked by the caller)
+void elem_outer_list(agc_context* c, const int32_t* ev, int64_t ne, const double* dg, const double* x, double* dh);
 
 // ------------------------------------------------------------------ PCG
 void spmv(agc_context* c, const Matrix& a, const double* x, double* y);

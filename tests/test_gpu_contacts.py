@@ -10,8 +10,9 @@ is bit-exact against the oracle's components; the FP64 solutions (coarsened,
 and fine with coarsen = 0) match the oracle's direct solve of the system
 with every element; the mixed solution is within 1e-5; the solution equals
 the one with the contacts in the static plan to rounding; post-coarsening
-iterates on the fine system with the contacts; the certified bound holds;
-malformed contacts and the unsupported combinations are rejected.
+iterates on the fine system with the contacts; the adjoint gives dL/dH for
+the contacts after the tets'; the certified bound holds; malformed contacts
+and the affine embedding with contacts are rejected.
 """
 import numpy as np
 import pytest
@@ -133,6 +134,45 @@ def test_post_coarsening_with_contacts(ctx, name):
     assert info.fine_rel_res < info.fine_rel_res0
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_with_contacts(ctx, name):
+    """agc_solve_backward with the contacts given per call: dL/dg and dL/dH
+    for every element (the tets, then the contacts) against the oracle's
+    adjoint of the system with every element, and the exact identities
+    L = <dL/dg, g> and sum_e <dL/dH_e, H_e> = -L."""
+    import torch
+    from oracle import adjoint as oadj
+    agc = binding()
+    d = setup(ctx, name)
+    p = d["p"]
+    n, ne = p["n_verts"], p["elem_verts"].shape[0]
+    w_np = np.random.default_rng(29).standard_normal((n, 3))
+    w = torch.from_numpy(w_np).to(ctx.device)
+    prob = agc.make_problem(d["mesh_tets"], d["edges"], d["tags"], d["eh_tets"], d["g"], d["rest"],
+                            contacts=(d["cv"], d["ch"]))
+    opts = agc.make_opts(rtol=1e-12, max_iter=100000)
+    x = torch.empty((n, 3), dtype=torch.float64, device=ctx.device)
+    mp = torch.empty(n, dtype=torch.int32, device=ctx.device)
+    info = agc.agc_solve(ctx, prob, opts, x, mp)
+    dg = torch.empty_like(x)
+    dh = torch.full((ne, 144), float("nan"), dtype=torch.float64, device=ctx.device)
+    agc.agc_solve_backward(ctx, prob, opts, mp, info.n_coarse, x, w, dg, dh)
+    m, nc = oagg.components(n, p["edges"], p["tags"])
+    _, dgr, dhr = oadj.adjoint(n, p["elem_verts"], p["elem_H"], p["g"], m, nc, w_np, dense=name == "small")
+    dg, dh = dg.cpu().numpy(), dh.cpu().numpy()
+    nt = p["n_tets"]
+    e_g = np.linalg.norm(dg - dgr) / np.linalg.norm(dgr)
+    e_t = np.linalg.norm(dh[:nt] - dhr[:nt]) / np.linalg.norm(dhr[:nt])
+    e_c = np.linalg.norm(dh[nt:] - dhr[nt:]) / np.linalg.norm(dhr[nt:])
+    log(f"[contacts] {name} adjoint: dg {e_g:.2e}, dH tets {e_t:.2e}, dH contacts {e_c:.2e}")
+    assert e_g <= 1e-6 and e_t <= 1e-6 and e_c <= 1e-6
+    L = float(np.sum(x.cpu().numpy() * w_np))
+    lin = float(np.sum(dg * p["g"]))
+    euler = float(np.sum(dh * p["elem_H"]))
+    assert abs(lin - L) <= 1e-8 * abs(L) + 1e-12 * np.abs(dg * p["g"]).sum()
+    assert abs(euler + L) <= 1e-8 * abs(L) + 1e-12 * np.abs(dh * p["elem_H"]).sum()
+
+
 def test_contact_set_changes_between_calls(ctx):
     """One context, one tet plan, three calls whose contact sets shrink
     (all 300, the first 120, none) and a fourth with all of them again: each
@@ -176,11 +216,6 @@ def test_rejected(ctx):
                             contacts=(d["cv"], d["ch"]))
     with pytest.raises(agc.AgcError):
         agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-8, affine_threshold=8), x)
-    mp = torch.empty(p["n_verts"], dtype=torch.int32, device=ctx.device)
-    info = agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-10), x, mp)
-    with pytest.raises(agc.AgcError):
-        agc.agc_solve_backward(ctx, prob, agc.make_opts(rtol=1e-10), mp, info.n_coarse, x, d["g"],
-                               torch.empty_like(x), None)
     # the context still works
     x2, _, _ = solve(ctx, d, rtol=1e-10)
     assert rel(x2, d["ref_c"]["x"]) <= 1e-7
