@@ -301,9 +301,8 @@ typedef struct {
   const int32_t* contact_verts; /* [n_contacts][4] int32, 4 distinct ids in
                               [0, n_verts) (AGC_ERR_BAD_INPUT otherwise)      */
   const double* contact_H; /* [n_contacts][144] float64 row-major, symmetric;
-                              with contacts, affine_threshold must be 0
-                              (AGC_ERR_INVALID_ARG); post-coarsening iterates
-                              on the fine system with them, and
+                              they join the affine-embedded system and the
+                              fine system of post-coarsening too, and
                               agc_solve_backward returns their dL/dH after
                               the mesh's                                      */
 } agc_problem;

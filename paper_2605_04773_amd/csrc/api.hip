@@ -204,7 +204,7 @@ SolveResult coarse_solve(agc_context* c, const agc_problem* p, const agc_solve_o
   agc::Matrix* A32 = mixed ? &c->solve_a : nullptr;
   const agc::Contacts x = contacts_of(p);
   if (R.am) {
-    agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32);
+    agc::assemble_coarse_affine(c, mesh, p->elem_H, *R.am, A64, A32, false, x);
   } else if (R.map) {
     agc::assemble_coarse(c, mesh, p->elem_H, AGC_F64, R.map, R.n_c, AGC_F64, A64, A32, false, x);
   } else if (x.n > 0) {
@@ -543,7 +543,6 @@ agc_status agc_solve(agc_context* c, const agc_problem* p, const agc_solve_opts*
   const agc::Mesh& mesh = p->mesh->m;
   const int32_t n = mesh.n_verts;
   AGC_REQUIRE(o->coarsen == 0 || p->n_edges == 0 || (p->edges && p->tags), "edges/tags null");
-  AGC_REQUIRE(p->n_contacts == 0 || o->affine_threshold == 0, "contact elements need affine_threshold = 0");
   Timer tm(c, o->timing != 0);
   struct KernelTiming {   // on for this call only, also when it throws
     agc_context* c;

@@ -856,6 +856,43 @@ __global__ void k_aff_keys(const int32_t* __restrict__ fr, const int32_t* __rest
   }
 }
 
+// The same keys for the per-call elements' upper pairs (items nf + 10 e + q,
+// as in k_contact_keys; vertex pair (v_a, v_b) of upper pair q = (a, b)).
+__global__ void k_aff_contact_keys(const int32_t* __restrict__ xv, int64_t nx, int32_t n,
+                                   const int32_t* __restrict__ map, int32_t n_c, const int32_t* __restrict__ newlab,
+                                   int32_t n3, int nb, int64_t nf, uint64_t* __restrict__ keys,
+                                   uint32_t* __restrict__ vals, unsigned* err) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 10 * nx; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = t / 10;
+    int a, b;
+    upper_pair((int)(t - 10 * e), a, b);
+    const int32_t va = xv[4 * e + a], vb = xv[4 * e + b];
+    const int64_t item = nf + t;
+    if (va < 0 || va >= n || vb < 0 || vb >= n || (a != b && va == vb)) {
+      atomicOr(err, kErrElem);
+      keys[item] = 0;
+      vals[item] = (uint32_t)(item * 4);
+      continue;
+    }
+    const int32_t mi = map[va], mj = map[vb];
+    if (mi < 0 || mi >= n_c || mj < 0 || mj >= n_c) {
+      atomicOr(err, kErrMap);
+      keys[item] = 0;
+      vals[item] = (uint32_t)(item * 4);
+      continue;
+    }
+    const int32_t ci = newlab[mi], cj = newlab[mj];
+    uint32_t o;
+    int32_t lo, hi;
+    if (ci < cj) { lo = ci; hi = cj; o = 0; }
+    else if (ci > cj) { lo = cj; hi = ci; o = 1; }
+    else { lo = hi = ci; o = (a == b) ? 0u : 2u; }
+    const uint64_t aff = hi >= n3 ? 1ull : 0ull;
+    keys[item] = (aff << nb) | ((uint64_t)lo * (uint64_t)n_c + (uint64_t)hi);
+    vals[item] = (uint32_t)(item * 4) | o;
+  }
+}
+
 // first position whose key has bit nb set (the caller presets *split = n)
 __global__ void k_aff_split(const uint64_t* __restrict__ keys, int64_t n, int nb, int64_t* split) {
   const uint64_t t = 1ull << nb;
@@ -880,6 +917,8 @@ struct AffineOp {
   int a;                     // row sub-block of this pass
   double* U;                 // planes [36][us]: 9 b + (3 r + s)
   int64_t us;
+  const int32_t* xv;         // per-call elements (items nf + 10 e + q): ids and blocks, or null
+  const double* xH;
   // homogeneous rest coordinate in the node's frame (a 3-DoF node: (0, 0, 0, 1))
   __device__ void xbar(int32_t v, bool big, double x[4]) const {
     if (big) {
@@ -895,10 +934,25 @@ struct AffineOp {
     const uint32_t code = payload[k];
     const int64_t f = code >> 2;
     const uint32_t o = code & 3u;
-    const int32_t i = fr[f], j = fc[f];
+    int32_t i, j;
     double b[9], bt[9];
+    if (f < nf) {
+      i = fr[f];
+      j = fc[f];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) b[q] = F[(int64_t)q * nf + f];
+      for (int q = 0; q < 9; ++q) b[q] = F[(int64_t)q * nf + f];
+    } else {
+      const int64_t t = f - nf, e = t / 10;
+      int pa, pb;
+      upper_pair((int)(t - 10 * e), pa, pb);
+      i = xv[4 * e + pa];
+      j = xv[4 * e + pb];
+      const double* h = xH + e * 144 + 36 * pa + 3 * pb;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) b[3 * r + q] = h[12 * r + q];
+    }
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -1012,39 +1066,47 @@ __global__ void k_aff_sorted(const uint64_t* __restrict__ sk, const uint32_t* __
 }
 
 void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* eh, const AffineMap& am, Matrix& out,
-                            Matrix* out32, bool reuse_upper) {
+                            Matrix* out32, bool reuse_upper, const Contacts& x) {
+  AGC_REQUIRE(x.n == 0 || (x.verts && x.H), "contact elements need ids and blocks");
   const int64_t nf = m.nf;
+  const int64_t ni = nf + 10 * x.n;   // items: the fine upper blocks, then the per-call elements' upper pairs
+  AGC_REQUIRE(ni < (int64_t(1) << 30), "too many fine blocks and contact pairs");
   const int32_t n_c = am.n_c, n3 = am.n3, n_flat = am.n_flat;
   double* F = reuse_upper ? upper_ready(c, m) : fine_upper<double>(c, m, eh, AGC_F64);
-  uint64_t* k1 = c->ws.get<uint64_t>("asm.k1", nf);
-  uint64_t* k2 = c->ws.get<uint64_t>("asm.k2", nf);
-  uint32_t* v1 = c->ws.get<uint32_t>("asm.v1", nf);
-  uint32_t* v2 = c->ws.get<uint32_t>("asm.v2", nf);
+  uint64_t* k1 = c->ws.get<uint64_t>("asm.k1", ni);
+  uint64_t* k2 = c->ws.get<uint64_t>("asm.k2", ni);
+  uint32_t* v1 = c->ws.get<uint32_t>("asm.v1", ni);
+  uint32_t* v2 = c->ws.get<uint32_t>("asm.v2", ni);
   const int nb = bits_for((uint64_t)n_c * (uint64_t)n_c - 1);
   err_reset(c);
   k_aff_keys<<<grid_stride_blocks(nf), kWG, 0, c->stream>>>((const int32_t*)m.fu_row.p, (const int32_t*)m.fu_col.p,
                                                            nf, am.map, n_c, am.newlab, n3, nb, k1, v1, c->d_err);
   AGC_LAUNCH_CHECK();
-  const bool alt = radix_sort_u64(c, k1, v1, k2, v2, nf, nb + 1, "aasm.sort");
+  if (x.n > 0) {
+    k_aff_contact_keys<<<grid_stride_blocks(10 * x.n), kWG, 0, c->stream>>>(x.verts, x.n, m.n_verts, am.map, n_c,
+                                                                            am.newlab, n3, nb, nf, k1, v1, c->d_err);
+    AGC_LAUNCH_CHECK();
+  }
+  const bool alt = radix_sort_u64(c, k1, v1, k2, v2, ni, nb + 1, "aasm.sort");
   uint64_t* sk = alt ? k2 : k1;
   uint32_t* sv = alt ? v2 : v1;
   uint64_t* uk = alt ? k1 : k2;   // free buffer for the unique keys
   int64_t* dsplit = c->ws.get<int64_t>("aasm.split", 1);
-  k_set_i64<<<1, 1, 0, c->stream>>>(dsplit, nf);
-  k_aff_split<<<grid_stride_blocks(nf), kWG, 0, c->stream>>>(sk, nf, nb, dsplit);
+  k_set_i64<<<1, 1, 0, c->stream>>>(dsplit, ni);
+  k_aff_split<<<grid_stride_blocks(ni), kWG, 0, c->stream>>>(sk, ni, nb, dsplit);
   AGC_LAUNCH_CHECK();
   int64_t split = 0;
   AGC_HIP(hipMemcpyAsync(&split, dsplit, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   AGC_HIP(hipStreamSynchronize(c->stream));
   // the 3-DoF pairs
-  double* U9 = c->ws.get<double>("aasm.U9", 9 * nf);   // CoarseOp writes planes of stride nf
+  double* U9 = c->ws.get<double>("aasm.U9", 9 * ni);   // CoarseOp writes planes of stride ni
   int64_t nu9 = 0;
   if (split > 0) {
-    CoarseOp<double> op(sv, F, nf, U9, nf, nullptr);
+    CoarseOp<double> op(sv, F, nf, U9, ni, x.H);
     nu9 = seg_reduce<9, double, uint64_t, CoarseOp<double>>(c, sk, split, op, uk, true, "aasm.seg9");
   }
   // the pairs with a 12-DoF node: four passes of four sub-blocks
-  const int64_t na = nf - split;
+  const int64_t na = ni - split;
   int64_t nua = 0;
   double* UA[4] = {nullptr, nullptr, nullptr, nullptr};
   uint64_t* uka = c->ws.get<uint64_t>("aasm.uka", na > 0 ? na : 1);
@@ -1052,7 +1114,7 @@ void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* eh, con
     for (int a = 0; a < 4; ++a) {
       UA[a] = c->ws.get<double>("aasm.UA" + std::to_string(a), 36 * na);
       AffineOp op{sv + split, F, nf, (const int32_t*)m.fu_row.p, (const int32_t*)m.fu_col.p, am.map, am.newlab,
-                  n3, am.rest, am.rep, a, UA[a], na};
+                  n3, am.rest, am.rep, a, UA[a], na, x.verts, x.H};
       const int64_t cnt = seg_reduce<36, double, uint64_t, AffineOp>(c, sk + split, na, op, a == 0 ? uka : nullptr,
                                                                       a == 0, "aasm.seg36");
       if (a == 0) nua = cnt;
@@ -1078,7 +1140,7 @@ void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* eh, con
   uint32_t* fp2 = c->ws.get<uint32_t>("aasm.fp2", nu);
   double* UC = c->ws.get<double>("aasm.UC", 9 * nu);
   if (nu9 > 0) {
-    k_aff_plain<<<grid_stride_blocks(nu9), kWG, 0, c->stream>>>(uk, nu9, n_c, n_flat, U9, nf, fk1, UC, nu);
+    k_aff_plain<<<grid_stride_blocks(nu9), kWG, 0, c->stream>>>(uk, nu9, n_c, n_flat, U9, ni, fk1, UC, nu);
     AGC_LAUNCH_CHECK();
   }
   if (nua > 0) {

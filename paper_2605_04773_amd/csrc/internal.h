@@ -213,7 +213,8 @@ void assemble_coarse(agc_context* c, const Mesh& m, const void* elem_h, int32_t 
 // A = P^T H P in the flat 3-block layout of `am` (float64 sums; out32 as for
 // assemble_coarse)
 void assemble_coarse_affine(agc_context* c, const Mesh& m, const double* elem_h, const AffineMap& am,
-                            Matrix& out, Matrix* out32 = nullptr, bool reuse_upper = false);
+                            Matrix& out, Matrix* out32 = nullptr, bool reuse_upper = false,
+                            const Contacts& x = Contacts{});
 // dH_e = -(dg_e)(x_e)^T
 void elem_outer(agc_context* c, const Mesh& m, const double* dg, const double* x, double* dh);
 // the same over a list of elements ([ne][4] ids, checked by the caller)

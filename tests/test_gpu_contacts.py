@@ -11,8 +11,8 @@ and fine with coarsen = 0) match the oracle's direct solve of the system
 with every element; the mixed solution is within 1e-5; the solution equals
 the one with the contacts in the static plan to rounding; post-coarsening
 iterates on the fine system with the contacts; the adjoint gives dL/dH for
-the contacts after the tets'; the certified bound holds; malformed contacts
-and the affine embedding with contacts are rejected.
+the contacts after the tets'; the affine embedding takes them; the certified
+bound holds; malformed contacts are rejected.
 """
 import numpy as np
 import pytest
@@ -173,6 +173,41 @@ def test_adjoint_with_contacts(ctx, name):
     assert abs(euler + L) <= 1e-8 * abs(L) + 1e-12 * np.abs(dh * p["elem_H"]).sum()
 
 
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_affine_with_contacts(ctx, name, precision):
+    """The adaptive affine embedding (Sec. 4.2, Eq. 4) with the contacts given
+    per call: node counts as the oracle's classification; FP64 at rtol 1e-10:
+    the oracle's coarse residual P^T (g - H x) of the system with every
+    element <= 1e-8 of P^T g; the error against the oracle's direct solve <=
+    1e-5; the same solution as with the contacts in the static plan (1e-10)."""
+    from oracle import affine as oaff
+    from oracle import galerkin as ogal
+    from oracle import solve as osol
+    agc = binding()
+    d = setup(ctx, name)
+    p = d["p"]
+    thr = 16   # every aggregate above it spans 3-D (a planar one would make the embedded system singular)
+    m, nc = oagg.components(p["n_verts"], p["edges"], p["tags"])
+    a_c, b_c, cls, pm = oaff.coarse_system(p, m, nc, thr)
+    x_ref = oaff.prolongate(pm, osol.solve_sparse(a_c, b_c.reshape(-1)))
+    prec = agc.AGC_PREC_MIXED if precision == "mixed" else agc.AGC_PREC_FP64
+    rtol = 1e-10 if precision == "fp64" else 1e-7
+    x, mp, info = solve(ctx, d, precision=prec, rtol=rtol, affine_threshold=thr)
+    xs, _, info_s = solve(ctx, d, per_call=False, precision=prec, rtol=rtol, affine_threshold=thr)
+    err = rel(x, x_ref)
+    log(f"[contacts] {name} affine {precision}: n12 {info.n_affine}, block rows {info.n_blocks}, error {err:.2e}, "
+        f"vs static plan {rel(x, xs):.2e}")
+    assert np.array_equal(mp, m)
+    assert info.n_affine == cls["n12"] > 0 and info.n_blocks == cls["n_flat"] == info_s.n_blocks
+    if precision == "fp64":
+        h = ogal.fine_hessian(p["n_verts"], p["elem_verts"], p["elem_H"])
+        r_c = pm.T @ (p["g"].reshape(-1) - h @ x.reshape(-1))
+        assert np.linalg.norm(r_c) <= 1e-8 * np.linalg.norm(b_c)
+        assert rel(x, xs) <= 1e-10
+    assert err <= 1e-5
+
+
 def test_contact_set_changes_between_calls(ctx):
     """One context, one tet plan, three calls whose contact sets shrink
     (all 300, the first 120, none) and a fourth with all of them again: each
@@ -214,8 +249,6 @@ def test_rejected(ctx):
         agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-8), x)
     prob = agc.make_problem(d["mesh_tets"], d["edges"], d["tags"], d["eh_tets"], d["g"], d["rest"],
                             contacts=(d["cv"], d["ch"]))
-    with pytest.raises(agc.AgcError):
-        agc.agc_solve(ctx, prob, agc.make_opts(rtol=1e-8, affine_threshold=8), x)
     # the context still works
     x2, _, _ = solve(ctx, d, rtol=1e-10)
     assert rel(x2, d["ref_c"]["x"]) <= 1e-7
