@@ -589,21 +589,27 @@ def agc_solve_backward(ctx: Context, prob: agc_problem, opts: agc_solve_opts, ma
 class AgcSolve(torch.autograd.Function):
     """x = P A_c^{-1} P^T g with A_c = sum_e (S_e P)^T H_e (S_e P); differentiable in g and H_e.
 
-    forward(g [n,3] f64, elem_H [n_e,144] f64, mesh, edges, tags, opts) -> x [n,3].
-    Only the map (and x) are kept for backward; the coarse matrix is assembled
-    again there.
+    forward(g [n,3] f64, elem_H [n_e,144] f64, mesh, edges, tags, opts,
+            contact_verts [n_x,4] int32 = None, contact_H [n_x,144] f64 = None) -> x [n,3].
+    The contact elements (this call's, beside the mesh's) are differentiable
+    too.  Only the map (and x) are kept for backward; the coarse matrix is
+    assembled again there.
     """
 
     @staticmethod
-    def forward(fctx, g, elem_H, mesh, edges, tags, opts):
+    def forward(fctx, g, elem_H, mesh, edges, tags, opts, contact_verts=None, contact_H=None):
         ctx = mesh.ctx
         g = g.contiguous()
         elem_H = elem_H.contiguous()
+        contacts = None
+        if contact_H is not None:
+            contacts = (contact_verts.contiguous(), contact_H.contiguous())
         x = torch.empty_like(g)
         mp = torch.empty(mesh.n_verts, dtype=torch.int32, device=g.device)
-        prob = make_problem(mesh, edges, tags, elem_H, g)
+        prob = make_problem(mesh, edges, tags, elem_H, g, contacts=contacts)
         info = agc_solve(ctx, prob, opts, x, mp)
-        fctx.save_for_backward(g, elem_H, mp, x)
+        saved = (g, elem_H, mp, x) + (contacts if contacts is not None else ())
+        fctx.save_for_backward(*saved)
         fctx.mesh, fctx.edges, fctx.tags, fctx.opts = mesh, edges, tags, opts
         fctx.n_coarse = info.n_coarse
         fctx.mark_non_differentiable(mp)
@@ -611,15 +617,23 @@ class AgcSolve(torch.autograd.Function):
 
     @staticmethod
     def backward(fctx, dx):
-        g, elem_H, mp, x = fctx.saved_tensors
+        saved = fctx.saved_tensors
+        g, elem_H, mp, x = saved[:4]
+        contacts = (saved[4], saved[5]) if len(saved) > 4 else None
         mesh = fctx.mesh
         dx = dx.contiguous()
         dg = torch.empty_like(g)
         need_h = fctx.needs_input_grad[1]
-        dH = torch.empty_like(elem_H) if need_h else None
-        prob = make_problem(mesh, fctx.edges, fctx.tags, elem_H, g)
+        need_c = contacts is not None and fctx.needs_input_grad[7]
+        n_e = elem_H.shape[0]
+        n_x = contacts[1].shape[0] if contacts is not None else 0
+        # the library writes dL/dH for the mesh's elements, then the contacts'
+        dH = torch.empty((n_e + n_x, 144), dtype=torch.float64, device=g.device) if (need_h or need_c) else None
+        prob = make_problem(mesh, fctx.edges, fctx.tags, elem_H, g, contacts=contacts)
         agc_solve_backward(mesh.ctx, prob, fctx.opts, mp, fctx.n_coarse, x, dx, dg, dH)
-        return dg, dH, None, None, None, None
+        d_mesh = dH[:n_e] if need_h else None
+        d_contact = dH[n_e:] if need_c else None
+        return dg, d_mesh, None, None, None, None, None, d_contact
 
 
 def check_single_hip_runtime() -> list[str]:

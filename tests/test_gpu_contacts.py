@@ -208,6 +208,35 @@ def test_affine_with_contacts(ctx, name, precision):
     assert err <= 1e-5
 
 
+def test_autograd_with_contacts(ctx):
+    """AgcSolve with the contacts given per call: the gradients of g, of the
+    mesh's element blocks and of the contact blocks against the oracle's
+    adjoint of the system with every element."""
+    import torch
+    from oracle import adjoint as oadj
+    agc = binding()
+    d = setup(ctx, "small")
+    p = d["p"]
+    n, nt = p["n_verts"], p["n_tets"]
+    w_np = np.random.default_rng(31).standard_normal((n, 3))
+    w = torch.from_numpy(w_np).to(ctx.device)
+    g = d["g"].clone().requires_grad_(True)
+    eh = d["eh_tets"].clone().requires_grad_(True)
+    ch = d["ch"].clone().requires_grad_(True)
+    x = agc.AgcSolve.apply(g, eh, d["mesh_tets"], d["edges"], d["tags"], agc.make_opts(rtol=1e-12, max_iter=100000),
+                           d["cv"], ch)
+    (x * w).sum().backward()
+    torch.cuda.synchronize()
+    m, nc = oagg.components(n, p["edges"], p["tags"])
+    xr, dgr, dhr = oadj.adjoint(n, p["elem_verts"], p["elem_H"], p["g"], m, nc, w_np, dense=True)
+    log(f"[contacts] autograd: x {rel(x.detach().cpu().numpy(), xr):.2e}, dg {rel(g.grad.cpu().numpy(), dgr):.2e}, "
+        f"dH tets {rel(eh.grad.cpu().numpy(), dhr[:nt]):.2e}, dH contacts {rel(ch.grad.cpu().numpy(), dhr[nt:]):.2e}")
+    assert rel(x.detach().cpu().numpy(), xr) <= 1e-8
+    assert rel(g.grad.cpu().numpy(), dgr) <= 1e-6
+    assert rel(eh.grad.cpu().numpy(), dhr[:nt]) <= 1e-6
+    assert rel(ch.grad.cpu().numpy(), dhr[nt:]) <= 1e-6
+
+
 def test_contact_set_changes_between_calls(ctx):
     """One context, one tet plan, three calls whose contact sets shrink
     (all 300, the first 120, none) and a fourth with all of them again: each
