@@ -113,6 +113,10 @@ def test_fine_with_contacts(ctx, name):
     assert np.array_equal(mp, np.arange(d["p"]["n_verts"]))
     assert info.nnzb == info_s.nnzb
     assert e <= 1e-8 and rel(x, xs) <= 1e-10
+    agc = binding()
+    xm, _, _ = solve(ctx, d, coarsen=0, precision=agc.AGC_PREC_MIXED, rtol=1e-9)
+    log(f"[contacts] {name} fine mixed: error {rel(xm, d['ref_f']['x']):.2e}")
+    assert rel(xm, d["ref_f"]["x"]) <= 1e-5
 
 
 @pytest.mark.parametrize("name", list(CASES))
