@@ -297,7 +297,9 @@ typedef struct {
                               Newton iteration (Sec. 3; Alg. overview), each
                               a 12x12 block over 4 vertices whose pairs enter
                               the Galerkin sum on each call without the mesh's
-                              static plan (0 = none)                          */
+                              static plan (0 = none; 10 n_contacts plus the
+                              mesh's fine upper blocks stay below 2^30,
+                              AGC_ERR_INVALID_ARG otherwise)                  */
   const int32_t* contact_verts; /* [n_contacts][4] int32, 4 distinct ids in
                               [0, n_verts) (AGC_ERR_BAD_INPUT otherwise)      */
   const double* contact_H; /* [n_contacts][144] float64 row-major, symmetric;
